@@ -1,0 +1,164 @@
+/*
+ * gsf.h -- C ABI of libgsf, the MI355X (gfx950) hot path of a filter-based
+ * HI spectral-line source finder (Westerlund & Harris, "Performance Analysis
+ * of GPU-Accelerated Filter-Based Source Finding for HI Spectral Line Image
+ * Data", Experimental Astronomy).
+ *
+ * The path: a bank of separable 3-D Gaussian filters applied to a spectral
+ * cube (Eq. 2, §2.1), a per-voxel local mean and standard deviation of each
+ * filtered cube over a box around the voxel (§3.3), and the selection of
+ * voxels above mean + k * std (§1, §3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  A cube of dims (nx, ny, nz) is one contiguous array, x slowest and
+ *   z (the spectral axis) contiguous: voxel (x, y, z) sits at linear index
+ *   (x*ny + y)*nz + z (§3.1: X is the major axis and Z the minor axis).
+ * Memory.  Every data pointer is a DEVICE pointer on the current HIP device,
+ *   owned by the caller: inputs, outputs and workspace.  The library never
+ *   allocates or frees device memory in these calls and keeps no pointer
+ *   after a call returns.  Data pointers must be 16-byte aligned; mask
+ *   pointers 8-byte aligned.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Calls validate their arguments synchronously, enqueue kernels on
+ *   `stream` and return; results are valid once the stream has been
+ *   synchronised.  Calls that overlap on one stream are ordered by it.
+ * Errors.  Arguments are checked before anything is enqueued; an invalid
+ *   call returns a non-zero gsf_status and leaves every output untouched.
+ *   A failed launch returns GSF_ERR_DEVICE.  gsf_last_error() gives a
+ *   human-readable detail for the calling thread.  The library never aborts
+ *   and never prints.
+ * Filters.  Taps per axis are g[o] = exp(-o^2 / (2 sigma^2)) / sum, for
+ *   o = -r..r, r = ceil(truncate * sigma) evaluated in FP64 (point-sampled,
+ *   unit-sum, box-truncated); the 3-D filter is gxy (x) gxy (x) gz.  The image
+ *   is zero outside the cube.  r must not exceed GSF_MAX_RADIUS.
+ * Windows.  The statistics window of length B along an axis covers offsets
+ *   [-floor(B/2), -floor(B/2) + B - 1] around the voxel, clipped to the cube;
+ *   n(v) is the product of the clipped lengths.  Standard deviations are
+ *   population values (divide by n).
+ * Masks.  One bit per voxel, packed along z: each (x, y) row holds
+ *   W = ceil(nz/64) uint64 words, bit j of word w is voxel z = 64*w + j; pad
+ *   bits are 0.  Word index of (x, y, w) is (x*ny + y)*W + w.
+ */
+#ifndef GSF_H
+#define GSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSF_MAX_RADIUS 64     /* largest filter radius r (taps 2r+1 = 129) */
+#define GSF_MAX_BOX 4096      /* largest statistics window length per axis */
+
+typedef enum gsf_status {
+    GSF_OK = 0,
+    GSF_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size, sigma, box, k, overlap */
+    GSF_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+    GSF_ERR_WORKSPACE = 3,    /* workspace smaller than the *_workspace_size figure */
+    GSF_ERR_DEVICE = 4,       /* a HIP call or kernel launch failed */
+    GSF_ERR_BUDGET = 5        /* request larger than an imposed memory budget */
+} gsf_status;
+
+typedef enum gsf_dtype {
+    GSF_F32 = 0,              /* IEEE binary32 */
+    GSF_F16 = 1,              /* IEEE binary16 (storage only; not accepted yet) */
+    GSF_BF16 = 2              /* bfloat16 (storage only; not accepted yet) */
+} gsf_dtype;
+
+typedef struct gsf_dims {
+    int64_t nx, ny, nz;       /* x slowest, z contiguous; each >= 1 */
+} gsf_dims;
+
+typedef struct gsf_filter {
+    double sigma_xy;          /* spatial sigma (x and y), pixels, > 0 */
+    double sigma_z;           /* spectral sigma, channels, > 0 */
+    double truncate;          /* radius r = ceil(truncate * sigma); 3.0 usual */
+} gsf_filter;
+
+typedef struct gsf_box {
+    int32_t bx, by, bz;       /* statistics window lengths, 1..GSF_MAX_BOX */
+} gsf_box;
+
+typedef struct gsf_cube {
+    const void *data;         /* device pointer to the cube */
+    gsf_dtype dtype;          /* storage type of data */
+    gsf_dims dims;            /* dims of the array at `data` */
+    int32_t halo[3];          /* input-only border per side; must be 0 in this build */
+} gsf_cube;
+
+/* ---- Filtering: Eq. 2 (§2.1), c_u[x][y][z] = sum_o d[x+o_x][y+o_y][z+o_z] f[o] ---- */
+
+/* Bytes of device workspace gsf_filter3d needs for a cube of dims d and
+ * filter f.  Pure host computation. */
+gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *bytes);
+
+/* out = Eq. 2 applied to `in` with filter *f (zero outside the cube).
+ * in, out: nx*ny*nz elements of in_t / out_t (both GSF_F32 in this build);
+ * they must not overlap.  ws: at least gsf_filter3d_workspace_size bytes
+ * (may be NULL when that figure is 0).  FP32 arithmetic, taps summed in the
+ * fixed order -r..r per axis. */
+gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_filter *f,
+                        void *out, gsf_dtype out_t, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Local statistics: §3.3, mean and std over a range around each voxel ---- */
+
+/* Bytes of device workspace gsf_local_stats needs.  Pure host computation. */
+gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes);
+
+/* mean[v] = (1/n) sum_W F,  stdev[v] = sqrt(max(0, (1/n) sum_W (F-s)^2 - ((1/n) sum_W (F-s))^2))
+ * over the clipped window W(v) of box b, s a shift computed on the device
+ * from F.  F: nx*ny*nz elements of t (GSF_F32).  mean, stdev: nx*ny*nz
+ * floats; either may be NULL if not wanted (not both).  Outputs must not
+ * overlap F or each other. */
+gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b,
+                           float *mean, float *stdev, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Selection: F > mean + k*std (§1, §3.3) ---- */
+
+/* mask bit of v = F[v] > thr[v], thr = (double)mean[v] + k * (double)stdev[v]
+ * evaluated in FP64 with each operation rounded once (no fused multiply-add),
+ * comparison strict, F promoted exactly.  mask: nx*ny*ceil(nz/64) words
+ * (layout above).  Given identical inputs the result is bit-exact. */
+gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const float *stdev,
+                         gsf_dims d, double k, uint64_t *mask, void *stream);
+
+/* ---- The whole path over a batch of cubes and a filter bank ---- */
+
+/* Bytes of device workspace gsf_find needs for this batch.  Pure host. */
+gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
+                                   int32_t nfilt, gsf_box b, size_t *bytes);
+
+/* For each cube c and filter j: F = Eq. 2, local mean/std over box b (§3.3),
+ * mask = F > mean + k*std, with the same definitions as the three calls
+ * above (the mask equals gsf_threshold of the F, mean and std produced here).
+ * masks[c*nfilt + j]: mask of cube c, filter j (required).
+ * F_out, mean_out, std_out: NULL, or arrays of ncubes*nfilt device pointers
+ * (each may be NULL) receiving the filtered cube (F32), local mean and local
+ * std.  ws: at least gsf_find_workspace_size bytes. */
+gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                    gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
+                    float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* ---- Helpers ---- */
+
+/* Number of uint64 mask words for dims d: nx*ny*ceil(nz/64); -1 if invalid. */
+int64_t gsf_mask_words(gsf_dims d);
+
+/* Static description of a status code. */
+const char *gsf_status_string(gsf_status s);
+
+/* Detail of the last failing call on the calling thread ("" if none). */
+const char *gsf_last_error(void);
+
+/* Library version string. */
+const char *gsf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSF_H */

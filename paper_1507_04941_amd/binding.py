@@ -1,0 +1,281 @@
+"""ctypes binding of libgsf (include/gsf.h) for torch tensors on a ROCm device.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors must be contiguous, on the current HIP device, and of the
+dtype the call expects; torch supplies device memory and the stream
+(``torch.cuda.current_stream().cuda_stream``).  When ``libgsf.so`` is missing
+this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsf.so")
+
+GSF_OK, GSF_ERR_INVALID_ARG, GSF_ERR_UNSUPPORTED, GSF_ERR_WORKSPACE, GSF_ERR_DEVICE, GSF_ERR_BUDGET = range(6)
+GSF_F32, GSF_F16, GSF_BF16 = 0, 1, 2
+GSF_MAX_RADIUS = 64
+GSF_MAX_BOX = 4096
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Filter(ctypes.Structure):
+    _fields_ = [("sigma_xy", ctypes.c_double), ("sigma_z", ctypes.c_double),
+                ("truncate", ctypes.c_double)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32)]
+
+
+class Cube(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int), ("dims", Dims),
+                ("halo", ctypes.c_int32 * 3)]
+
+
+class GsfError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"gsf status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_ST = ctypes.c_int
+
+# (name, restype, argtypes) for every symbol include/gsf.h declares.
+SIGNATURES = [
+    ("gsf_filter3d_workspace_size", _ST, [Dims, ctypes.POINTER(Filter), ctypes.POINTER(_SZ)]),
+    ("gsf_filter3d", _ST, [_P, ctypes.c_int, Dims, ctypes.POINTER(Filter), _P, ctypes.c_int, _P,
+                           _SZ, _P]),
+    ("gsf_local_stats_workspace_size", _ST, [Dims, Box, ctypes.POINTER(_SZ)]),
+    ("gsf_local_stats", _ST, [_P, ctypes.c_int, Dims, Box, _P, _P, _P, _SZ, _P]),
+    ("gsf_threshold", _ST, [_P, ctypes.c_int, _P, _P, Dims, ctypes.c_double, _P, _P]),
+    ("gsf_find_workspace_size", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter),
+                                      ctypes.c_int32, Box, ctypes.POINTER(_SZ)]),
+    ("gsf_find", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter), ctypes.c_int32,
+                       Box, ctypes.c_double, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                       ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    ("gsf_mask_words", ctypes.c_int64, [Dims]),
+    ("gsf_status_string", ctypes.c_char_p, [_ST]),
+    ("gsf_last_error", ctypes.c_char_p, []),
+    ("gsf_version", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """Open libgsf.so (built in-tree by ``build.build()``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int) -> None:
+    if st != GSF_OK:
+        raise GsfError(st, lib().gsf_last_error().decode())
+
+
+def _dims(shape) -> Dims:
+    nx, ny, nz = (int(s) for s in shape)
+    return Dims(nx, ny, nz)
+
+
+def _filter(f) -> Filter:
+    if isinstance(f, Filter):
+        return f
+    t = float(f[2]) if len(f) > 2 else 3.0
+    return Filter(float(f[0]), float(f[1]), t)
+
+
+def _box(b) -> Box:
+    if isinstance(b, Box):
+        return b
+    if isinstance(b, int):
+        return Box(b, b, b)
+    bx, by, bz = (int(v) for v in b)
+    return Box(bx, by, bz)
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _cube(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dim() != 3:
+        raise ValueError(f"{name} must be a 3-D tensor (nx, ny, nz)")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def mask_words(shape) -> int:
+    nx, ny, nz = (int(s) for s in shape)
+    return nx * ny * ((nz + 63) // 64)
+
+
+def empty_mask(shape, device) -> torch.Tensor:
+    nx, ny, nz = (int(s) for s in shape)
+    return torch.empty((nx, ny, (nz + 63) // 64), dtype=torch.int64, device=device)
+
+
+def unpack_mask(words, shape) -> np.ndarray:
+    """Packed mask words (nx, ny, W) -> bool array (nx, ny, nz)."""
+    nx, ny, nz = (int(s) for s in shape)
+    w = words.detach().cpu().numpy() if isinstance(words, torch.Tensor) else np.asarray(words)
+    w = np.ascontiguousarray(w.reshape(nx, ny, -1)).view(np.uint8)
+    bits = np.unpackbits(w, axis=2, bitorder="little")
+    return bits[:, :, :nz].astype(bool)
+
+
+def version() -> str:
+    return lib().gsf_version().decode()
+
+
+def filter3d_workspace_size(shape, f) -> int:
+    n = _SZ(0)
+    _check(lib().gsf_filter3d_workspace_size(_dims(shape), ctypes.byref(_filter(f)), ctypes.byref(n)))
+    return int(n.value)
+
+
+def filter3d(cube: torch.Tensor, f, out: torch.Tensor | None = None,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. 2: the cube filtered by one (sigma_xy, sigma_z[, truncate]) Gaussian."""
+    cube = _cube(cube, "cube")
+    if out is None:
+        out = torch.empty_like(cube)
+    _cube(out, "out")
+    need = filter3d_workspace_size(cube.shape, f)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cube.device)
+    _check(lib().gsf_filter3d(cube.data_ptr(), GSF_F32, _dims(cube.shape), ctypes.byref(_filter(f)),
+                              out.data_ptr(), GSF_F32, ws.data_ptr(), ws.numel(),
+                              _stream(cube.device)))
+    return out
+
+
+def local_stats_workspace_size(shape, box) -> int:
+    n = _SZ(0)
+    _check(lib().gsf_local_stats_workspace_size(_dims(shape), _box(box), ctypes.byref(n)))
+    return int(n.value)
+
+
+def local_stats(F: torch.Tensor, box, want_mean: bool = True, want_std: bool = True,
+                ws: torch.Tensor | None = None):
+    """§3.3: per-voxel local mean and std of F over the clipped box window."""
+    F = _cube(F, "F")
+    mean = torch.empty_like(F) if want_mean else None
+    std = torch.empty_like(F) if want_std else None
+    need = local_stats_workspace_size(F.shape, box)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=F.device)
+    _check(lib().gsf_local_stats(F.data_ptr(), GSF_F32, _dims(F.shape), _box(box),
+                                 mean.data_ptr() if mean is not None else None,
+                                 std.data_ptr() if std is not None else None,
+                                 ws.data_ptr(), ws.numel(), _stream(F.device)))
+    return mean, std
+
+
+def threshold(F: torch.Tensor, mean: torch.Tensor, std: torch.Tensor, k: float,
+              mask: torch.Tensor | None = None) -> torch.Tensor:
+    """Selection F > mean + k*std, packed along z into int64 words (nx, ny, W)."""
+    F, mean, std = _cube(F, "F"), _cube(mean, "mean"), _cube(std, "std")
+    if mask is None:
+        mask = empty_mask(F.shape, F.device)
+    _check(lib().gsf_threshold(F.data_ptr(), GSF_F32, mean.data_ptr(), std.data_ptr(),
+                               _dims(F.shape), float(k), mask.data_ptr(), _stream(F.device)))
+    return mask
+
+
+def _cube_structs(cubes):
+    arr = (Cube * len(cubes))()
+    for i, c in enumerate(cubes):
+        c = _cube(c, f"cubes[{i}]")
+        arr[i].data = c.data_ptr()
+        arr[i].dtype = GSF_F32
+        arr[i].dims = _dims(c.shape)
+        arr[i].halo[0] = arr[i].halo[1] = arr[i].halo[2] = 0
+    return arr
+
+
+def find_workspace_size(cubes, filters, box) -> int:
+    carr = _cube_structs(cubes)
+    farr = (Filter * len(filters))(*[_filter(f) for f in filters])
+    n = _SZ(0)
+    _check(lib().gsf_find_workspace_size(carr, len(cubes), farr, len(filters), _box(box),
+                                         ctypes.byref(n)))
+    return int(n.value)
+
+
+class FindPlan:
+    """Pre-marshalled gsf_find call over fixed cubes and output buffers, so a
+    timed loop only re-issues the C call."""
+
+    def __init__(self, cubes, filters, box, k: float, want_F: bool = False,
+                 want_stats: bool = False):
+        self.cubes = [_cube(c, f"cubes[{i}]") for i, c in enumerate(cubes)]
+        self.filters = [tuple(f) for f in filters]
+        dev = self.cubes[0].device
+        nc, nf = len(self.cubes), len(self.filters)
+        self.masks = [[empty_mask(c.shape, dev) for _ in range(nf)] for c in self.cubes]
+        self.F = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_F else None
+        self.mean = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_stats else None
+        self.std = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_stats else None
+        self._carr = _cube_structs(self.cubes)
+        self._farr = (Filter * nf)(*[_filter(f) for f in self.filters])
+        self._box = _box(box)
+        self.k = float(k)
+
+        def ptrs(grid):
+            if grid is None:
+                return None
+            return (_P * (nc * nf))(*[grid[c][j].data_ptr() for c in range(nc) for j in range(nf)])
+
+        self._m = ptrs(self.masks)
+        self._F = ptrs(self.F)
+        self._mu = ptrs(self.mean)
+        self._sd = ptrs(self.std)
+        need = find_workspace_size(self.cubes, self.filters, box)
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.device = dev
+
+    def run(self, stream: int | None = None) -> None:
+        s = _stream(self.device) if stream is None else stream
+        _check(lib().gsf_find(self._carr, len(self.cubes), self._farr, len(self.filters), self._box,
+                              self.k, self._m, self._F, self._mu, self._sd, self.ws.data_ptr(),
+                              self.ws.numel(), s))
+
+
+def find(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False) -> dict:
+    """The whole path over a batch of cubes: for each cube and filter, Eq. 2,
+    local mean/std (§3.3) and the mask F > mean + k*std.
+
+    Returns {'mask': [[words]], 'F': [[...]] | None, 'mean': ..., 'std': ...}
+    indexed [cube][filter]."""
+    if isinstance(cubes, torch.Tensor):
+        cubes = [cubes]
+    plan = FindPlan(cubes, filters, box, k, want_F=want_F, want_stats=want_stats)
+    plan.run()
+    return {"mask": plan.masks, "F": plan.F, "mean": plan.mean, "std": plan.std}

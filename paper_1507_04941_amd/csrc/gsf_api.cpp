@@ -1,0 +1,377 @@
+// gsf_api.cpp -- the C ABI declared in include/gsf.h: argument validation,
+// host-side filter taps, workspace sizing and the launch schedule.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gsf_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gsf_status fail(gsf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+gsf_status ok()
+{
+    g_err.clear();
+    return GSF_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Limits keep every grid dimension and index product in range: a dispatch's
+// grid size is a 32-bit count of work-items per dimension, and the widest
+// grids launch nx*ny blocks of 256 work-items.
+constexpr int64_t kMaxRows = (int64_t)1 << 24;      // nx*ny, exclusive
+constexpr int64_t kMaxNz = (int64_t)1 << 23;        // ceil(nz/256) blocks along grid y
+constexpr int64_t kMaxVoxels = (int64_t)1 << 40;
+
+gsf_status check_dims(gsf_dims d)
+{
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1)
+        return fail(GSF_ERR_INVALID_ARG, "dims must be >= 1 (got %lld x %lld x %lld)",
+                    (long long)d.nx, (long long)d.ny, (long long)d.nz);
+    if (d.nx >= kMaxRows || d.ny >= kMaxRows || d.nx * d.ny >= kMaxRows || d.nz > kMaxNz ||
+        d.nx * d.ny > kMaxVoxels / d.nz)
+        return fail(GSF_ERR_INVALID_ARG, "dims too large (%lld x %lld x %lld)", (long long)d.nx,
+                    (long long)d.ny, (long long)d.nz);
+    return GSF_OK;
+}
+
+// Radius r = ceil(truncate * sigma), FP64, as the filter definition states.
+gsf_status check_filter(const gsf_filter *f)
+{
+    if (!f) return fail(GSF_ERR_INVALID_ARG, "filter pointer is NULL");
+    if (!(std::isfinite(f->sigma_xy) && f->sigma_xy > 0.0) ||
+        !(std::isfinite(f->sigma_z) && f->sigma_z > 0.0))
+        return fail(GSF_ERR_INVALID_ARG, "sigma must be finite and > 0 (got %g, %g)",
+                    f->sigma_xy, f->sigma_z);
+    if (!(std::isfinite(f->truncate) && f->truncate > 0.0))
+        return fail(GSF_ERR_INVALID_ARG, "truncate must be finite and > 0 (got %g)", f->truncate);
+    const double rxy = std::ceil(f->truncate * f->sigma_xy);
+    const double rz = std::ceil(f->truncate * f->sigma_z);
+    if (rxy > GSF_MAX_RADIUS || rz > GSF_MAX_RADIUS)
+        return fail(GSF_ERR_INVALID_ARG, "filter radius exceeds %d (r_xy=%g, r_z=%g)",
+                    GSF_MAX_RADIUS, rxy, rz);
+    return GSF_OK;
+}
+
+gsf_status check_box(gsf_box b)
+{
+    if (b.bx < 1 || b.by < 1 || b.bz < 1 || b.bx > GSF_MAX_BOX || b.by > GSF_MAX_BOX ||
+        b.bz > GSF_MAX_BOX)
+        return fail(GSF_ERR_INVALID_ARG, "box lengths must be in [1, %d] (got %d, %d, %d)",
+                    GSF_MAX_BOX, b.bx, b.by, b.bz);
+    return GSF_OK;
+}
+
+gsf_status check_dtype(gsf_dtype t, const char *what)
+{
+    if (t == GSF_F32) return GSF_OK;
+    if (t == GSF_F16 || t == GSF_BF16)
+        return fail(GSF_ERR_UNSUPPORTED, "%s: only GSF_F32 storage is implemented", what);
+    return fail(GSF_ERR_INVALID_ARG, "%s: unknown dtype %d", what, (int)t);
+}
+
+gsf_status check_ptr(const void *p, size_t align, const char *what)
+{
+    if (!p) return fail(GSF_ERR_INVALID_ARG, "%s is NULL", what);
+    if (!aligned(p, align))
+        return fail(GSF_ERR_INVALID_ARG, "%s is not %zu-byte aligned", what, align);
+    return GSF_OK;
+}
+
+// Sampled unit-sum Gaussian, offsets -r..r, computed in FP64 and rounded to FP32.
+gsf::Taps make_taps(double sigma, double truncate)
+{
+    gsf::Taps t{};
+    const int r = (int)std::ceil(truncate * sigma);
+    double w[gsf::kMaxTaps];
+    double sum = 0.0;
+    for (int o = -r; o <= r; ++o) {
+        w[o + r] = std::exp(-(double)(o * o) / (2.0 * sigma * sigma));
+        sum += w[o + r];
+    }
+    for (int i = 0; i <= 2 * r; ++i) t.g[i] = (float)(w[i] / sum);
+    t.r = r;
+    return t;
+}
+
+gsf::Dims to_dims(gsf_dims d) { return gsf::Dims{d.nx, d.ny, d.nz}; }
+gsf::Box to_box(gsf_box b) { return gsf::Box{b.bx, b.by, b.bz}; }
+
+size_t cube_bytes(gsf_dims d) { return align_up((size_t)(d.nx * d.ny * d.nz) * sizeof(float)); }
+
+// Workspace pieces shared by the statistics schedule.
+size_t stats_ws(gsf_dims d)
+{
+    return 4 * cube_bytes(d) + align_up(gsf::kShiftBlocks * sizeof(double)) +
+           align_up(sizeof(double));
+}
+
+struct StatsWs {
+    float *w1, *w2, *w3, *w4;
+    double *partials, *shift;
+};
+
+StatsWs carve_stats(char *p, gsf_dims d)
+{
+    StatsWs w;
+    const size_t c = cube_bytes(d);
+    w.w1 = (float *)p; p += c;
+    w.w2 = (float *)p; p += c;
+    w.w3 = (float *)p; p += c;
+    w.w4 = (float *)p; p += c;
+    w.partials = (double *)p; p += align_up(gsf::kShiftBlocks * sizeof(double));
+    w.shift = (double *)p;
+    return w;
+}
+
+gsf_status device_status(hipError_t e, const char *what)
+{
+    if (e != hipSuccess)
+        return fail(GSF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gsf_version(void) { return "gsf 0.1.0 (gfx950)"; }
+
+const char *gsf_status_string(gsf_status s)
+{
+    switch (s) {
+    case GSF_OK: return "ok";
+    case GSF_ERR_INVALID_ARG: return "invalid argument";
+    case GSF_ERR_UNSUPPORTED: return "unsupported";
+    case GSF_ERR_WORKSPACE: return "workspace too small";
+    case GSF_ERR_DEVICE: return "device error";
+    case GSF_ERR_BUDGET: return "over memory budget";
+    }
+    return "unknown status";
+}
+
+const char *gsf_last_error(void) { return g_err.c_str(); }
+
+int64_t gsf_mask_words(gsf_dims d)
+{
+    if (check_dims(d) != GSF_OK) return -1;
+    return to_dims(d).words();
+}
+
+gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *bytes)
+{
+    gsf_status st;
+    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_dims(d)) || (st = check_filter(f))) return st;
+    *bytes = cube_bytes(d);
+    return ok();
+}
+
+gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_filter *f, void *out,
+                        gsf_dtype out_t, void *ws, size_t ws_bytes, void *stream)
+{
+    gsf_status st;
+    if ((st = check_dims(d)) || (st = check_filter(f)) || (st = check_ptr(in, 16, "in")) ||
+        (st = check_ptr(out, 16, "out")) || (st = check_dtype(in_t, "in_t")) ||
+        (st = check_dtype(out_t, "out_t")))
+        return st;
+    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t need = cube_bytes(d);
+    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((st = check_ptr(ws, 16, "ws"))) return st;
+    if (overlaps(in, nb, out, nb) || overlaps(in, nb, ws, need) || overlaps(out, nb, ws, need))
+        return fail(GSF_ERR_INVALID_ARG, "in, out and ws must not overlap");
+    const gsf::Taps txy = make_taps(f->sigma_xy, f->truncate);
+    const gsf::Taps tz = make_taps(f->sigma_z, f->truncate);
+    return device_status(gsf::launch_filter3d((const float *)in, (float *)out, (float *)ws,
+                                              to_dims(d), txy, tz, (hipStream_t)stream),
+                         "gsf_filter3d launch");
+}
+
+gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes)
+{
+    gsf_status st;
+    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_dims(d)) || (st = check_box(b))) return st;
+    *bytes = stats_ws(d);
+    return ok();
+}
+
+gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b, float *mean,
+                           float *stdev, void *ws, size_t ws_bytes, void *stream)
+{
+    gsf_status st;
+    if ((st = check_dims(d)) || (st = check_box(b)) || (st = check_ptr(F, 16, "F")) ||
+        (st = check_dtype(t, "t")))
+        return st;
+    if (!mean && !stdev) return fail(GSF_ERR_INVALID_ARG, "mean and stdev are both NULL");
+    if (mean && (st = check_ptr(mean, 16, "mean"))) return st;
+    if (stdev && (st = check_ptr(stdev, 16, "stdev"))) return st;
+    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t need = stats_ws(d);
+    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((st = check_ptr(ws, 16, "ws"))) return st;
+    if (overlaps(F, nb, mean, nb) || overlaps(F, nb, stdev, nb) || overlaps(mean, nb, stdev, nb) ||
+        overlaps(ws, need, F, nb) || overlaps(ws, need, mean, nb) || overlaps(ws, need, stdev, nb))
+        return fail(GSF_ERR_INVALID_ARG, "F, mean, stdev and ws must not overlap");
+    const gsf::Dims dd = to_dims(d);
+    const StatsWs w = carve_stats((char *)ws, d);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = gsf::launch_mean((const float *)F, dd, w.partials, w.shift, s);
+    if (e == hipSuccess)
+        e = gsf::launch_stats((const float *)F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
+                              mean, stdev, nullptr, 0.0, s);
+    return device_status(e, "gsf_local_stats launch");
+}
+
+gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const float *stdev,
+                         gsf_dims d, double k, uint64_t *mask, void *stream)
+{
+    gsf_status st;
+    if ((st = check_dims(d)) || (st = check_ptr(F, 16, "F")) || (st = check_dtype(t, "t")) ||
+        (st = check_ptr(mean, 16, "mean")) || (st = check_ptr(stdev, 16, "stdev")) ||
+        (st = check_ptr(mask, 8, "mask")))
+        return st;
+    if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
+    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t mb = (size_t)to_dims(d).words() * sizeof(uint64_t);
+    if (overlaps(mask, mb, F, nb) || overlaps(mask, mb, mean, nb) || overlaps(mask, mb, stdev, nb))
+        return fail(GSF_ERR_INVALID_ARG, "mask must not overlap its inputs");
+    return device_status(gsf::launch_threshold((const float *)F, mean, stdev, to_dims(d), k, mask,
+                                               (hipStream_t)stream),
+                         "gsf_threshold launch");
+}
+
+namespace {
+
+gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                       gsf_box b, gsf_dims *largest)
+{
+    gsf_status st;
+    if (!cubes || ncubes < 1) return fail(GSF_ERR_INVALID_ARG, "need at least one cube");
+    if (!f || nfilt < 1) return fail(GSF_ERR_INVALID_ARG, "need at least one filter");
+    if ((st = check_box(b))) return st;
+    for (int32_t j = 0; j < nfilt; ++j)
+        if ((st = check_filter(&f[j]))) return st;
+    int64_t best = 0;
+    for (int32_t c = 0; c < ncubes; ++c) {
+        const gsf_cube &q = cubes[c];
+        if ((st = check_dims(q.dims))) return st;
+        if ((st = check_dtype(q.dtype, "cube dtype"))) return st;
+        if (q.halo[0] < 0 || q.halo[1] < 0 || q.halo[2] < 0)
+            return fail(GSF_ERR_INVALID_ARG, "cube %d: negative halo", c);
+        if (q.halo[0] || q.halo[1] || q.halo[2])
+            return fail(GSF_ERR_UNSUPPORTED, "cube %d: halos are not implemented", c);
+        const int64_t v = q.dims.nx * q.dims.ny * q.dims.nz;
+        if (v > best) { best = v; *largest = q.dims; }
+    }
+    return GSF_OK;
+}
+
+size_t find_ws(gsf_dims largest) { return stats_ws(largest) + cube_bytes(largest); }
+
+}  // namespace
+
+gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
+                                   int32_t nfilt, gsf_box b, size_t *bytes)
+{
+    gsf_status st;
+    gsf_dims largest{};
+    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
+    *bytes = find_ws(largest);
+    return ok();
+}
+
+gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                    gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
+                    float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
+                    void *stream)
+{
+    gsf_status st;
+    gsf_dims largest{};
+    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
+    if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
+    if (!masks) return fail(GSF_ERR_INVALID_ARG, "masks is NULL");
+    const size_t need = find_ws(largest);
+    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((st = check_ptr(ws, 16, "ws"))) return st;
+    // Validate every output pointer before enqueueing anything.
+    for (int32_t c = 0; c < ncubes; ++c) {
+        const gsf_cube &q = cubes[c];
+        if ((st = check_ptr(q.data, 16, "cube data"))) return st;
+        const size_t nb = (size_t)(q.dims.nx * q.dims.ny * q.dims.nz) * sizeof(float);
+        const size_t mb = (size_t)to_dims(q.dims).words() * sizeof(uint64_t);
+        if (overlaps(ws, need, q.data, nb))
+            return fail(GSF_ERR_INVALID_ARG, "cube %d overlaps the workspace", c);
+        for (int32_t j = 0; j < nfilt; ++j) {
+            const int64_t o = (int64_t)c * nfilt + j;
+            if ((st = check_ptr(masks[o], 8, "masks[i]"))) return st;
+            const void *outs[4] = {masks[o], F_out ? F_out[o] : nullptr,
+                                   mean_out ? mean_out[o] : nullptr, std_out ? std_out[o] : nullptr};
+            const size_t sizes[4] = {mb, nb, nb, nb};
+            for (int a = 1; a < 4; ++a)
+                if (outs[a] && (st = check_ptr(outs[a], 16, "F/mean/std output"))) return st;
+            for (int a = 0; a < 4; ++a) {
+                if (!outs[a]) continue;
+                if (overlaps(outs[a], sizes[a], q.data, nb) || overlaps(outs[a], sizes[a], ws, need))
+                    return fail(GSF_ERR_INVALID_ARG, "output of cube %d filter %d overlaps input or ws",
+                                c, j);
+                for (int b2 = a + 1; b2 < 4; ++b2)
+                    if (outs[b2] && overlaps(outs[a], sizes[a], outs[b2], sizes[b2]))
+                        return fail(GSF_ERR_INVALID_ARG, "outputs of cube %d filter %d overlap", c, j);
+            }
+        }
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const StatsWs w = carve_stats(base, largest);
+    float *Fbuf = (float *)(base + stats_ws(largest));
+    for (int32_t c = 0; c < ncubes; ++c) {
+        const gsf_cube &q = cubes[c];
+        const gsf::Dims dd = to_dims(q.dims);
+        for (int32_t j = 0; j < nfilt; ++j) {
+            const int64_t o = (int64_t)c * nfilt + j;
+            float *F = (F_out && F_out[o]) ? (float *)F_out[o] : Fbuf;
+            const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
+            const gsf::Taps tz = make_taps(f[j].sigma_z, f[j].truncate);
+            hipError_t e = gsf::launch_filter3d((const float *)q.data, F, w.w1, dd, txy, tz, s);
+            if (e == hipSuccess) e = gsf::launch_mean(F, dd, w.partials, w.shift, s);
+            if (e == hipSuccess)
+                e = gsf::launch_stats(F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
+                                      mean_out ? mean_out[o] : nullptr,
+                                      std_out ? std_out[o] : nullptr, masks[o], k, s);
+            if (e != hipSuccess) return device_status(e, "gsf_find launch");
+        }
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal interface between the C-ABI layer (gsf_api.cpp) and the kernels
+// (gsf_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsf.h"
+
+namespace gsf {
+
+constexpr int kMaxTaps = 2 * GSF_MAX_RADIUS + 1;
+
+// FP32 taps of one axis, offsets -r..r at g[0..2r].  Passed to kernels by value.
+struct Taps {
+    float g[kMaxTaps];
+    int r;
+};
+
+struct Dims {
+    int64_t nx, ny, nz;
+    int64_t voxels() const { return nx * ny * nz; }
+    int64_t words() const { return nx * ny * ((nz + 63) / 64); }
+};
+
+// Window of length B: offsets [lo, lo + B - 1] with lo = -floor(B/2).
+struct Box {
+    int bx, by, bz;
+};
+
+// Number of per-block partial sums used for the global shift.
+constexpr int kShiftBlocks = 1024;
+
+// Kernel launchers.  All enqueue on `s` and return hipGetLastError().
+hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
+                           const Taps &tz, hipStream_t s);
+// shift[0] = mean of F (FP64), computed with a fixed reduction order.
+hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s);
+// Local statistics and (optionally) the mask in one schedule.
+// ws1..ws4: four scratch cubes of d.voxels() floats.
+hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, float *ws1, float *ws2,
+                        float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
+                        double k, hipStream_t s);
+hipError_t launch_threshold(const float *F, const float *mean, const float *stdev, Dims d,
+                            double k, uint64_t *mask, hipStream_t s);
+
+}  // namespace gsf

@@ -1,0 +1,310 @@
+// gsf_kernels.hip -- HIP kernels for gfx950 (wave64).
+//
+// Filter: Eq. 2 of §2.1 as three 1-D passes (the 3-D Gaussian is the outer
+// product of its axis kernels).  Statistics: §3.3's per-voxel mean and
+// standard deviation over a box window, computed as three directional window
+// sums of F - s and (F - s)^2.  Selection: F > mean + k*std.
+#include <hip/hip_runtime.h>
+
+#include "gsf_internal.h"
+
+namespace gsf {
+namespace {
+
+constexpr int kBlock = 256;   // four wave64s along z
+
+// ---------------------------------------------------------------------------
+// Filter passes.  Each output sums its taps in order -r..r with FMA.
+// ---------------------------------------------------------------------------
+
+// Spectral (z) pass: a block stages one row segment plus its +-r halo in LDS
+// with coalesced loads, then every lane reads its 2r+1 neighbours from LDS.
+__global__ __launch_bounds__(kBlock) void k_zpass(const float *__restrict__ in,
+                                                  float *__restrict__ out, int64_t nz, Taps t)
+{
+    extern __shared__ float tile[];
+    const int r = t.r;
+    const int64_t row = blockIdx.x;
+    const int64_t z0 = (int64_t)blockIdx.y * kBlock;
+    const float *src = in + row * nz;
+    for (int i = threadIdx.x; i < kBlock + 2 * r; i += kBlock) {
+        const int64_t z = z0 - r + i;
+        tile[i] = (z >= 0 && z < nz) ? src[z] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t z = z0 + threadIdx.x;
+    if (z < nz) {
+        float acc = 0.0f;
+        for (int o = 0; o <= 2 * r; ++o) acc = fmaf(t.g[o], tile[threadIdx.x + o], acc);
+        out[row * nz + z] = acc;
+    }
+}
+
+// Pass along a strided axis (y: stride nz, x: stride ny*nz).  Lanes run
+// along z so every tap load is a coalesced row read.
+__global__ __launch_bounds__(kBlock) void k_strided_pass(const float *__restrict__ in,
+                                                         float *__restrict__ out, int64_t ny,
+                                                         int64_t nz, int axis_x, int64_t n_axis,
+                                                         Taps t)
+{
+    const int r = t.r;
+    const int64_t row = blockIdx.x;          // x*ny + y
+    const int64_t z = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+    if (z >= nz) return;
+    const int64_t y = row % ny, x = row / ny;
+    const int64_t pos = axis_x ? x : y;
+    const int64_t stride = axis_x ? ny * nz : nz;
+    const float *src = in + row * nz + z;
+    float acc = 0.0f;
+    for (int o = -r; o <= r; ++o) {
+        const int64_t p = pos + o;
+        if (p >= 0 && p < n_axis) acc = fmaf(t.g[o + r], src[(int64_t)o * stride], acc);
+    }
+    out[row * nz + z] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Global shift: mean of F with a fixed reduction tree (deterministic).
+// ---------------------------------------------------------------------------
+
+__device__ double block_sum(double v, double *lds)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_partial_sums(const float *__restrict__ F, int64_t V,
+                                                         double *__restrict__ partials)
+{
+    __shared__ double lds[kBlock];
+    const int64_t chunk = (V + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * chunk;
+    const int64_t b = a + chunk < V ? a + chunk : V;
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += (double)F[i];
+    const double tot = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_mean(const double *__restrict__ partials,
+                                                       int n, int64_t V, double *__restrict__ out)
+{
+    __shared__ double lds[kBlock];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += partials[i];
+    const double tot = block_sum(s, lds);
+    if (threadIdx.x == 0) out[0] = tot / (double)V;
+}
+
+// ---------------------------------------------------------------------------
+// Statistics: directional window sums.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t win_count(int64_t i, int64_t n, int B)
+{
+    int64_t lo = i - (B / 2);
+    int64_t hi = lo + B;
+    if (lo < 0) lo = 0;
+    if (hi > n) hi = n;
+    return hi - lo;
+}
+
+// z window sums of a = F - s and a^2, one row segment per block staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_zbox(const float *__restrict__ F, int64_t nz, int B,
+                                                 const double *__restrict__ shift,
+                                                 float *__restrict__ Z1, float *__restrict__ Z2)
+{
+    extern __shared__ float lds[];
+    float *a1 = lds;
+    float *a2 = lds + kBlock + B - 1;
+    const double s = shift[0];
+    const int lo = -(B / 2);
+    const int64_t row = blockIdx.x;
+    const int64_t z0 = (int64_t)blockIdx.y * kBlock;
+    const float *src = F + row * nz;
+    for (int i = threadIdx.x; i < kBlock + B - 1; i += kBlock) {
+        const int64_t z = z0 + lo + i;
+        double a = 0.0;
+        if (z >= 0 && z < nz) a = (double)src[z] - s;
+        a1[i] = (float)a;
+        a2[i] = (float)(a * a);
+    }
+    __syncthreads();
+    const int64_t z = z0 + threadIdx.x;
+    if (z < nz) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < B; ++j) {
+            s1 += (double)a1[threadIdx.x + j];
+            s2 += (double)a2[threadIdx.x + j];
+        }
+        Z1[row * nz + z] = (float)s1;
+        Z2[row * nz + z] = (float)s2;
+    }
+}
+
+// Running window sums along a strided axis (y or x), FP64 accumulators.
+// in/out indexed as base + p*stride for p = 0..n-1.
+__device__ __forceinline__ void running_axis(const float *__restrict__ in1,
+                                             const float *__restrict__ in2,
+                                             float *__restrict__ out1, float *__restrict__ out2,
+                                             int64_t n, int64_t stride, int B)
+{
+    const int64_t lo = -(B / 2);
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t p = 0; p < lo + B && p < n; ++p) {
+        s1 += (double)in1[p * stride];
+        s2 += (double)in2[p * stride];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (i > 0) {
+            const int64_t add = i + lo + B - 1;
+            const int64_t sub = i + lo - 1;
+            if (add < n) { s1 += (double)in1[add * stride]; s2 += (double)in2[add * stride]; }
+            if (sub >= 0) { s1 -= (double)in1[sub * stride]; s2 -= (double)in2[sub * stride]; }
+        }
+        out1[i * stride] = (float)s1;
+        out2[i * stride] = (float)s2;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ybox(const float *__restrict__ Z1,
+                                                 const float *__restrict__ Z2,
+                                                 float *__restrict__ Y1, float *__restrict__ Y2,
+                                                 int64_t ny, int64_t nz, int B)
+{
+    const int64_t x = blockIdx.x;
+    const int64_t z = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+    if (z >= nz) return;
+    const int64_t base = x * ny * nz + z;
+    running_axis(Z1 + base, Z2 + base, Y1 + base, Y2 + base, ny, nz, B);
+}
+
+// x window sums, then mean/std and the selection bit, packed by wave ballot.
+__global__ __launch_bounds__(kBlock) void k_xbox_final(
+    const float *__restrict__ Y1, const float *__restrict__ Y2, const float *__restrict__ F,
+    int64_t nx, int64_t ny, int64_t nz, Box b, const double *__restrict__ shift,
+    float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
+{
+#pragma clang fp contract(off)
+    const int64_t y = blockIdx.x;
+    const int64_t z = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+    const bool live = z < nz;
+    const int64_t plane = ny * nz;
+    const int64_t base = y * nz + (live ? z : 0);
+    const int64_t W = (nz + 63) / 64;
+    const double s = shift[0];
+    const int lo = -(b.bx / 2);
+    const double cyz = live ? (double)(win_count(y, ny, b.by) * win_count(z, nz, b.bz)) : 1.0;
+    double s1 = 0.0, s2 = 0.0;
+    if (live)
+        for (int64_t p = 0; p < lo + b.bx && p < nx; ++p) {
+            s1 += (double)Y1[base + p * plane];
+            s2 += (double)Y2[base + p * plane];
+        }
+    for (int64_t x = 0; x < nx; ++x) {
+        bool bit = false;
+        if (live) {
+            if (x > 0) {
+                const int64_t add = x + lo + b.bx - 1;
+                const int64_t sub = x + lo - 1;
+                if (add < nx) { s1 += (double)Y1[base + add * plane]; s2 += (double)Y2[base + add * plane]; }
+                if (sub >= 0) { s1 -= (double)Y1[base + sub * plane]; s2 -= (double)Y2[base + sub * plane]; }
+            }
+            const double n = cyz * (double)win_count(x, nx, b.bx);
+            const double m1 = s1 / n;
+            double var = s2 / n - m1 * m1;
+            if (var < 0.0) var = 0.0;
+            const float mf = (float)(s + m1);
+            const float sf = (float)sqrt(var);
+            const int64_t i = x * plane + base;
+            if (mean) mean[i] = mf;
+            if (stdev) stdev[i] = sf;
+            if (mask) {
+                const double thr = (double)mf + k * (double)sf;
+                bit = (double)F[i] > thr;
+            }
+        }
+        if (mask) {
+            const uint64_t word = __ballot(bit);
+            if ((threadIdx.x & 63) == 0 && (int64_t)blockIdx.y * kBlock + threadIdx.x < nz)
+                mask[(x * ny + y) * W + ((int64_t)blockIdx.y * kBlock + threadIdx.x) / 64] = word;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_threshold(const float *__restrict__ F,
+                                                      const float *__restrict__ mean,
+                                                      const float *__restrict__ stdev,
+                                                      int64_t nz, double k,
+                                                      uint64_t *__restrict__ mask)
+{
+#pragma clang fp contract(off)
+    const int64_t row = blockIdx.x;
+    const int64_t z = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+    const int64_t W = (nz + 63) / 64;
+    bool bit = false;
+    if (z < nz) {
+        const int64_t i = row * nz + z;
+        const double thr = (double)mean[i] + k * (double)stdev[i];
+        bit = (double)F[i] > thr;
+    }
+    const uint64_t word = __ballot(bit);
+    if ((threadIdx.x & 63) == 0 && z < nz) mask[row * W + z / 64] = word;
+}
+
+inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
+                           const Taps &tz, hipStream_t s)
+{
+    const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
+    // z: in -> out, y: out -> tmp, x: tmp -> out
+    hipLaunchKernelGGL(k_zpass, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s, in,
+                       out, d.nz, tz);
+    hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)out, tmp, d.ny,
+                       d.nz, 0, d.ny, txy);
+    hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, out, d.ny,
+                       d.nz, 1, d.nx, txy);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_partial_sums, dim3(kShiftBlocks), dim3(kBlock), 0, s, F, d.voxels(),
+                       partials);
+    hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, (const double *)partials,
+                       kShiftBlocks, d.voxels(), shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, float *ws1, float *ws2,
+                        float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
+                        double k, hipStream_t s)
+{
+    const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
+    hipLaunchKernelGGL(k_zbox, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), zlds, s,
+                       F, d.nz, b.bz, shift, ws1, ws2);
+    hipLaunchKernelGGL(k_ybox, dim3((unsigned)d.nx, ztiles(d.nz)), dim3(kBlock), 0, s,
+                       (const float *)ws1, (const float *)ws2, ws3, ws4, d.ny, d.nz, b.by);
+    hipLaunchKernelGGL(k_xbox_final, dim3((unsigned)d.ny, ztiles(d.nz)), dim3(kBlock), 0, s,
+                       (const float *)ws3, (const float *)ws4, F, d.nx, d.ny, d.nz, b, shift, mean,
+                       stdev, mask, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold(const float *F, const float *mean, const float *stdev, Dims d,
+                            double k, uint64_t *mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_threshold, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), 0,
+                       s, F, mean, stdev, d.nz, k, mask);
+    return hipGetLastError();
+}
+
+}  // namespace gsf

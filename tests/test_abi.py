@@ -1,0 +1,141 @@
+"""The C-ABI library loads, exports every symbol include/gsf.h declares, and
+its host-side validation returns the documented codes (no GPU needed: every
+call here fails validation before anything is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsf.h")
+
+torch = pytest.importorskip("torch")
+from paper_1507_04941_amd import binding as B  # noqa: E402
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1507_04941_amd import build
+        build.build()
+    return B.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+    bound = {s[0] for s in B.SIGNATURES}
+    assert set(names) == bound
+
+
+def test_status_strings(L):
+    for s in range(6):
+        assert L.gsf_status_string(s)
+    assert L.gsf_status_string(99) == b"unknown status"
+    assert L.gsf_version().startswith(b"gsf")
+
+
+def test_mask_words(L):
+    assert L.gsf_mask_words(B.Dims(2, 3, 64)) == 6
+    assert L.gsf_mask_words(B.Dims(2, 3, 65)) == 12
+    assert L.gsf_mask_words(B.Dims(1, 1, 1)) == 1
+    assert L.gsf_mask_words(B.Dims(0, 3, 65)) == -1
+
+
+def _ws_filter(dims, f):
+    n = ctypes.c_size_t(0)
+    st = B.lib().gsf_filter3d_workspace_size(dims, ctypes.byref(f), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_sizes(L):
+    st, n = _ws_filter(B.Dims(512, 512, 1024), B.Filter(4.0, 8.0, 3.0))
+    assert st == 0 and n >= 512 * 512 * 1024 * 4
+    n2 = ctypes.c_size_t(0)
+    assert L.gsf_local_stats_workspace_size(B.Dims(64, 64, 128), B.Box(32, 32, 32),
+                                            ctypes.byref(n2)) == 0
+    assert n2.value >= 4 * 64 * 64 * 128 * 4
+    cubes = (B.Cube * 2)()
+    cubes[0].data = 256
+    cubes[0].dims = B.Dims(64, 64, 128)
+    cubes[1].data = 256
+    cubes[1].dims = B.Dims(100, 10, 300)
+    filt = (B.Filter * 2)(B.Filter(1, 1, 3), B.Filter(2, 4, 3))
+    n3 = ctypes.c_size_t(0)
+    assert L.gsf_find_workspace_size(cubes, 2, filt, 2, B.Box(8, 8, 8), ctypes.byref(n3)) == 0
+    assert n3.value >= 5 * 100 * 10 * 300 * 4
+
+
+@pytest.mark.parametrize("dims,f,code", [
+    (B.Dims(0, 4, 4), B.Filter(1, 1, 3), B.GSF_ERR_INVALID_ARG),
+    (B.Dims(4, 4, -1), B.Filter(1, 1, 3), B.GSF_ERR_INVALID_ARG),
+    (B.Dims(4, 4, 4), B.Filter(0, 1, 3), B.GSF_ERR_INVALID_ARG),
+    (B.Dims(4, 4, 4), B.Filter(1, float("nan"), 3), B.GSF_ERR_INVALID_ARG),
+    (B.Dims(4, 4, 4), B.Filter(1, 1, float("inf")), B.GSF_ERR_INVALID_ARG),
+    (B.Dims(4, 4, 4), B.Filter(30, 1, 3), B.GSF_ERR_INVALID_ARG),       # radius 90 > 64
+    (B.Dims(1 << 20, 1 << 20, 4), B.Filter(1, 1, 3), B.GSF_ERR_INVALID_ARG),
+])
+def test_filter_validation(L, dims, f, code):
+    st, _ = _ws_filter(dims, f)
+    assert st == code
+    assert L.gsf_last_error()
+
+
+def test_calls_reject_bad_pointers_before_launch(L):
+    d = B.Dims(8, 8, 8)
+    f = B.Filter(1, 1, 3)
+    # NULL input
+    assert L.gsf_filter3d(None, 0, d, ctypes.byref(f), 4096, 0, 8192, 1 << 20, None) == 1
+    # misaligned output
+    assert L.gsf_filter3d(4096, 0, d, ctypes.byref(f), 4100, 0, 8192, 1 << 20, None) == 1
+    # workspace too small
+    assert L.gsf_filter3d(4096, 0, d, ctypes.byref(f), 65536, 0, 1 << 20, 16, None) == 3
+    # in/out overlap
+    assert L.gsf_filter3d(4096, 0, d, ctypes.byref(f), 4096 + 256, 0, 1 << 24, 1 << 20, None) == 1
+    # unsupported storage type
+    assert L.gsf_filter3d(4096, 1, d, ctypes.byref(f), 65536, 0, 1 << 20, 1 << 20, None) == 2
+    # unknown dtype
+    assert L.gsf_filter3d(4096, 7, d, ctypes.byref(f), 65536, 0, 1 << 20, 1 << 20, None) == 1
+    # threshold: non-finite k, null mask
+    assert L.gsf_threshold(4096, 0, 65536, 131072, d, float("nan"), 1 << 20, None) == 1
+    assert L.gsf_threshold(4096, 0, 65536, 131072, d, 4.0, None, None) == 1
+    # local stats: both outputs NULL, bad box
+    assert L.gsf_local_stats(4096, 0, d, B.Box(4, 4, 4), None, None, 1 << 24, 1 << 24, None) == 1
+    assert L.gsf_local_stats(4096, 0, d, B.Box(0, 4, 4), 65536, None, 1 << 24, 1 << 24, None) == 1
+    assert L.gsf_local_stats(4096, 0, d, B.Box(4, 4, 5000), 65536, None, 1 << 24, 1 << 24, None) == 1
+
+
+def test_find_validation(L):
+    cubes = (B.Cube * 1)()
+    cubes[0].data = 4096
+    cubes[0].dims = B.Dims(8, 8, 8)
+    filt = (B.Filter * 1)(B.Filter(1, 1, 3))
+    masks = (ctypes.c_void_p * 1)(1 << 20)
+    box = B.Box(4, 4, 4)
+    n = ctypes.c_size_t(0)
+    assert L.gsf_find_workspace_size(cubes, 1, filt, 1, box, ctypes.byref(n)) == 0
+    need = n.value
+    ws = 1 << 30
+    assert L.gsf_find(cubes, 0, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
+    assert L.gsf_find(cubes, 1, filt, 0, box, 4.0, masks, None, None, None, ws, need, None) == 1
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, None, None, None, None, ws, need, None) == 1
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need - 1, None) == 3
+    cubes[0].halo[2] = 2
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 2
+    cubes[0].halo[2] = -1
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
+    cubes[0].halo[2] = 0
+    cubes[0].dtype = 2
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 2
+    cubes[0].dtype = 0
+    masks2 = (ctypes.c_void_p * 1)(4096 + 64)  # mask overlaps the cube
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks2, None, None, None, ws, need, None) == 1

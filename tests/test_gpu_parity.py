@@ -1,0 +1,225 @@
+"""GPU parity: every entry point of libgsf against the FP64 oracle on the same
+seeded inputs, through the C ABI.  Sizes span several tiles with ragged tails
+and the degenerate shapes (dims below the filter radius, single voxels,
+boxes longer than the cube)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1507_04941_amd import binding as B
+from paper_1507_04941_amd import synth
+from tests.parity import (check_filtered, check_mask, check_stats, cube_scale, log, sigma_f)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _gpu(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.SMALL
+    return w, synth.workload_cube(w)
+
+
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_filter3d_small_workload(small, j):
+    w, d = small
+    f = w.filters[j]
+    log(f"filter3d {w.name} filter={f}")
+    Fg = B.filter3d(_gpu(d), f).cpu().numpy()
+    Fo = oracle.filter3d(d, *f)
+    worst = check_filtered(Fg, Fo, f, cube_scale(d))
+    log(f"  worst/bound={worst:.3g}")
+
+
+ODD = [
+    ((5, 7, 9), (2.0, 4.0)),          # every dim below the radius
+    ((1, 1, 1), (1.0, 1.0)),
+    ((3, 70, 257), (1.0, 2.0)),       # ragged z tail over two 256-tiles
+    ((33, 17, 300), (1.0, 8.0)),
+    ((2, 3, 64), (4.0, 8.0)),
+    ((40, 9, 65), (1.5, 2.5)),        # non-integer sigmas
+    ((70, 2, 1), (2.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("shape,f", ODD)
+def test_filter3d_odd_shapes(shape, f):
+    log(f"filter3d odd shape={shape} filter={f}")
+    d = synth.make_noise(shape, seed=sum(shape)) + 0.5
+    Fg = B.filter3d(_gpu(d), f).cpu().numpy()
+    Fo = oracle.filter3d(d, *f)
+    check_filtered(Fg, Fo, f, cube_scale(d))
+
+
+def test_filter3d_impulse_is_sampled_kernel():
+    log("filter3d impulse")
+    d = np.zeros((31, 29, 70), dtype=np.float32)
+    d[15, 14, 35] = 1.0
+    f = (2.0, 4.0)
+    Fg = B.filter3d(_gpu(d), f).cpu().numpy()
+    gxy, gz = oracle.taps(2.0), oracle.taps(4.0)
+    ref = np.zeros(d.shape)
+    ref[9:22, 8:21, 23:48] = gxy[:, None, None] * gxy[None, :, None] * gz[None, None, :]
+    np.testing.assert_allclose(Fg, ref, rtol=0, atol=1e-5 * ref.max())
+
+
+STATS_CASES = [
+    ((64, 64, 128), (32, 32, 32), 0.0),
+    ((20, 30, 200), (8, 6, 64), 0.0),
+    ((9, 5, 70), (16, 16, 16), 0.0),   # box longer than x and y
+    ((16, 16, 96), (5, 7, 9), 250.0),  # odd boxes, large offset (shift matters)
+    ((1, 1, 300), (1, 1, 64), 0.0),
+]
+
+
+@pytest.mark.parametrize("shape,box,offset", STATS_CASES)
+def test_local_stats_matches_oracle(shape, box, offset):
+    log(f"local_stats shape={shape} box={box} offset={offset}")
+    d = synth.make_cube(shape, n_sources=max(1, shape[0] * shape[1] * shape[2] // 30000), seed=7)
+    f = (1.0, 2.0)
+    Fin = (oracle.filter3d(d, *f) + offset).astype(np.float32)
+    mg, sg = B.local_stats(_gpu(Fin), box)
+    mo, so = oracle.local_stats(Fin.astype(np.float64), box)
+    floor = sigma_f(f) * cube_scale(d)
+    wm, ws = check_stats(mg.cpu().numpy(), sg.cpu().numpy(), mo, so, floor)
+    log(f"  worst mean/bound={wm:.3g} std/bound={ws:.3g}")
+
+
+def test_local_stats_constant_cube():
+    log("local_stats constant")
+    Fin = np.full((12, 10, 100), 3.25, dtype=np.float32)
+    mg, sg = B.local_stats(_gpu(Fin), (4, 4, 16))
+    assert np.all(mg.cpu().numpy() == 3.25)
+    assert np.all(sg.cpu().numpy() == 0.0)
+
+
+def _ties(n, seed):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal(n).astype(np.float32)
+    m = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    s = np.abs(rng.standard_normal(n) * 0.3).astype(np.float32)
+    # plant exact ties and one-ulp neighbours: mean=1, std=0.25, k=4 -> thr=2
+    t = rng.choice(n, size=n // 10, replace=False)
+    m[t] = 1.0
+    s[t] = 0.25
+    F[t] = np.array([2.0, np.nextafter(np.float32(2), np.float32(3)),
+                     np.nextafter(np.float32(2), np.float32(1))], dtype=np.float32)[np.arange(t.size) % 3]
+    z = rng.choice(n, size=n // 20, replace=False)
+    s[z] = 0.0
+    F[z] = m[z]
+    return F, m, s
+
+
+@pytest.mark.parametrize("shape", [(7, 9, 130), (64, 64, 128), (1, 1, 1), (3, 2, 64)])
+def test_threshold_bit_exact(shape):
+    log(f"threshold shape={shape}")
+    n = int(np.prod(shape))
+    F, m, s = (a.reshape(shape) for a in _ties(n, seed=n))
+    words = B.threshold(_gpu(F), _gpu(m), _gpu(s), 4.0)
+    got = B.unpack_mask(words, shape)
+    ref = oracle.threshold_f32(F, m, s, 4.0).astype(bool)
+    np.testing.assert_array_equal(got, ref)
+    # pad bits of the last word are zero
+    W = (shape[2] + 63) // 64
+    raw = words.cpu().numpy().reshape(shape[0], shape[1], W).view(np.uint64)
+    if shape[2] % 64:
+        assert np.all((raw[:, :, -1] >> np.uint64(shape[2] % 64)) == 0)
+
+
+def test_find_small_workload(small):
+    w, d = small
+    log(f"find {w.name}")
+    out = B.find(_gpu(d), w.filters, w.box, w.k, want_F=True, want_stats=True)
+    torch.cuda.synchronize()
+    ref = oracle.find(d, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    scale = cube_scale(d)
+    for j, f in enumerate(w.filters):
+        Fg = out["F"][0][j].cpu().numpy()
+        mg = out["mean"][0][j].cpu().numpy()
+        sg = out["std"][0][j].cpu().numpy()
+        check_filtered(Fg, ref["F"][j], f, scale, what=f"F[{j}]")
+        check_stats(mg, sg, ref["mean"][j], ref["std"][j], sigma_f(f) * scale, what=f"stats[{j}]")
+        mask_g = B.unpack_mask(out["mask"][0][j], d.shape)
+        band = check_mask(mask_g, ref["F"][j], ref["mean"][j], ref["std"][j], w.k, f, scale,
+                          what=f"mask[{j}]")
+        n_sel = int(mask_g.sum())
+        log(f"  filter {f}: selected {n_sel}, oracle {int(ref['mask'][j].sum())}, band {band}")
+        # the mask is the selection of the F, mean and std produced alongside it
+        again = B.threshold(out["F"][0][j], out["mean"][0][j], out["std"][0][j], w.k)
+        assert torch.equal(again, out["mask"][0][j])
+
+
+def test_find_masks_only_equals_full_outputs(small):
+    w, d = small
+    log("find masks-only vs full outputs")
+    g = _gpu(d)
+    a = B.find(g, w.filters, w.box, w.k)
+    b = B.find(g, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    for j in range(len(w.filters)):
+        assert torch.equal(a["mask"][0][j], b["mask"][0][j])
+
+
+def test_find_batch_equals_single_cubes():
+    log("find batch of uneven cubes")
+    shapes = [(20, 24, 130), (33, 8, 64), (5, 40, 300)]
+    cubes = [synth.make_cube(s, n_sources=3, seed=100 + i) for i, s in enumerate(shapes)]
+    filters = [(1.0, 2.0), (2.0, 4.0)]
+    box = (8, 8, 16)
+    gs = [_gpu(c) for c in cubes]
+    batch = B.find(gs, filters, box, 4.0, want_F=True, want_stats=True)
+    for i, g in enumerate(gs):
+        one = B.find(g, filters, box, 4.0, want_F=True, want_stats=True)
+        for j in range(len(filters)):
+            assert torch.equal(batch["mask"][i][j], one["mask"][0][j])
+            assert torch.equal(batch["F"][i][j], one["F"][0][j])
+            assert torch.equal(batch["mean"][i][j], one["mean"][0][j])
+        ref = oracle.find(cubes[i], filters, box, 4.0, want_F=True, want_stats=True)
+        for j, f in enumerate(filters):
+            check_filtered(batch["F"][i][j].cpu().numpy(), ref["F"][j], f, cube_scale(cubes[i]))
+            check_stats(batch["mean"][i][j].cpu().numpy(), batch["std"][i][j].cpu().numpy(),
+                        ref["mean"][j], ref["std"][j], sigma_f(f) * cube_scale(cubes[i]))
+
+
+def test_run_twice_bitwise_identical(small):
+    w, d = small
+    log("find run twice")
+    g = _gpu(d)
+    a = B.find(g, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    b = B.find(g, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    for key in ("mask", "F", "mean", "std"):
+        for j in range(len(w.filters)):
+            assert torch.equal(a[key][0][j], b[key][0][j]), key
+
+
+def test_outputs_stay_inside_their_buffers():
+    log("guard bands")
+    shape = (17, 13, 129)
+    n = int(np.prod(shape))
+    d = synth.make_noise(shape, seed=3)
+    pad = 4096
+    canary = np.float32(-1234.5)
+    big = torch.full((n + 2 * pad,), float(canary), dtype=torch.float32, device=DEV)
+    out = big[pad:pad + n].view(shape)
+    B.filter3d(_gpu(d), (2.0, 4.0), out=out)
+    mb = torch.full((n + 2 * pad,), float(canary), dtype=torch.float32, device=DEV)
+    sb = torch.full((n + 2 * pad,), float(canary), dtype=torch.float32, device=DEV)
+    ws = torch.empty(B.local_stats_workspace_size(shape, (8, 8, 8)), dtype=torch.uint8, device=DEV)
+    st = B.lib().gsf_local_stats(out.data_ptr(), 0, B._dims(shape), B._box((8, 8, 8)),
+                                 mb[pad:].data_ptr(), sb[pad:].data_ptr(), ws.data_ptr(),
+                                 ws.numel(), B._stream(out.device))
+    assert st == 0
+    W = (shape[2] + 63) // 64
+    words = shape[0] * shape[1] * W
+    mk = torch.full((words + 2 * 64,), -7, dtype=torch.int64, device=DEV)
+    B.threshold(out, mb[pad:pad + n].view(shape), sb[pad:pad + n].view(shape), 4.0,
+                mask=mk[64:64 + words].view(shape[0], shape[1], W))
+    torch.cuda.synchronize()
+    for buf in (big, mb, sb):
+        assert torch.all(buf[:pad] == canary) and torch.all(buf[pad + n:] == canary)
+    assert torch.all(mk[:64] == -7) and torch.all(mk[64 + words:] == -7)
