@@ -143,6 +143,26 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                     float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* ---- Kernel timing (measurement aid) ---- */
+
+/* While enabled (on != 0), every kernel the library enqueues is bracketed by
+ * two hipEvents recorded on the stream it runs on, so its duration can be
+ * read back afterwards.  Disabled by default; costs two event records per
+ * launch when on.  Enabling or disabling does not clear recorded data. */
+gsf_status gsf_profile_enable(int on);
+
+/* Drop every recorded launch. */
+gsf_status gsf_profile_reset(void);
+
+/* Synchronise the recorded events and aggregate them per kernel name.
+ * Returns the number of distinct kernels (0 if nothing was recorded), or -1
+ * if a HIP event call failed. */
+int32_t gsf_profile_collect(void);
+
+/* Entry i (0 <= i < last collect count) of the aggregate: kernel name
+ * (static string), number of launches and summed duration in milliseconds. */
+gsf_status gsf_profile_entry(int32_t i, const char **name, int64_t *launches, double *total_ms);
+
 /* ---- Helpers ---- */
 
 /* Number of uint64 mask words for dims d: nx*ny*ceil(nz/64); -1 if invalid. */

@@ -65,6 +65,11 @@ SIGNATURES = [
     ("gsf_find", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter), ctypes.c_int32,
                        Box, ctypes.c_double, ctypes.POINTER(_P), ctypes.POINTER(_P),
                        ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    ("gsf_profile_enable", _ST, [ctypes.c_int]),
+    ("gsf_profile_reset", _ST, []),
+    ("gsf_profile_collect", ctypes.c_int32, []),
+    ("gsf_profile_entry", _ST, [ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     ("gsf_mask_words", ctypes.c_int64, [Dims]),
     ("gsf_status_string", ctypes.c_char_p, [_ST]),
     ("gsf_last_error", ctypes.c_char_p, []),
@@ -266,6 +271,31 @@ class FindPlan:
         _check(lib().gsf_find(self._carr, len(self.cubes), self._farr, len(self.filters), self._box,
                               self.k, self._m, self._F, self._mu, self._sd, self.ws.data_ptr(),
                               self.ws.numel(), s))
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel with hipEvents on its stream (see gsf.h)."""
+    _check(lib().gsf_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(lib().gsf_profile_reset())
+
+
+def profile_collect() -> dict:
+    """{kernel name: (launches, total ms)} over the launches recorded so far."""
+    L = lib()
+    n = L.gsf_profile_collect()
+    if n < 0:
+        raise GsfError(GSF_ERR_DEVICE, "hipEvent query failed")
+    out = {}
+    for i in range(n):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(L.gsf_profile_entry(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)))
+        out[name.value.decode()] = (int(cnt.value), float(ms.value))
+    return out
 
 
 def find(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False) -> dict:

@@ -1,0 +1,190 @@
+// gsf_filter.hip -- the separable Gaussian filter (Eq. 2, §2.1) for gfx950.
+//
+// The 3-D filter is the outer product gxy (x) gxy (x) gz, so Eq. 2 is applied
+// as a spectral pass followed by a fused spatial pass:
+//   k_zpass_r<R>: T1 = gz * d along z (contiguous).  A block stages one row
+//     segment with its +-R halo in LDS using coalesced loads; every lane then
+//     holds a (4 + 2R)-wide window in registers (ds_read_b128) and produces 4
+//     consecutive outputs, so each staged value feeds up to 4(2R+1) FMAs.
+//   k_yx_r<R, P>: F = gxy * (gxy * T1 along y) along x.  A block owns a 64-wide
+//     z strip (one lane per z, coalesced rows) and 4 waves x P rows of y, and
+//     sweeps an x range plane by plane.  For each plane it forms the y-pass of
+//     its P points from 2R + P row loads, then scatters that value into a
+//     register ring of 2R+1 partial x sums per point; the oldest sum is
+//     complete and written after every plane.  T1 is read once and F written
+//     once; nothing else touches memory.
+// Taps are compile-time indexed kernel arguments (scalar registers).  Every
+// output sums its taps in ascending offset order, as in the definition.
+#include <hip/hip_runtime.h>
+
+#include "gsf_internal.h"
+
+namespace gsf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kZOut = 4 * kThreads;   // z outputs per k_zpass_r block
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ in,
+                                                      float *__restrict__ out, int64_t nz, Taps t)
+{
+    constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
+    __shared__ float4 tile4[kZOut / 4 + NW + 1];
+    float *tile = reinterpret_cast<float *>(tile4);
+    const int64_t row = blockIdx.x;
+    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    const float *src = in + row * nz;
+    for (int i = threadIdx.x; i < 4 * (kZOut / 4 + NW + 1); i += kThreads) {
+        const int64_t z = z0 - R + i;
+        tile[i] = (z >= 0 && z < nz) ? src[z] : 0.0f;
+    }
+    __syncthreads();
+    float w[4 * NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        const float4 q = tile4[threadIdx.x + j];
+        w[4 * j] = q.x;
+        w[4 * j + 1] = q.y;
+        w[4 * j + 2] = q.z;
+        w[4 * j + 3] = q.w;
+    }
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int o = 0; o <= 2 * R; ++o) {
+        const float g = t.g[o];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
+    }
+    const int64_t z = z0 + 4 * threadIdx.x;
+    float *dst = out + row * nz + z;
+    if (z + 3 < nz && (((uintptr_t)dst) & 15) == 0) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (z + k < nz) dst[k] = acc[k];
+    }
+}
+
+template <int R, int P>
+__global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
+                                                   float *__restrict__ F, int64_t nx, int64_t ny,
+                                                   int64_t nz, int64_t xchunk, Taps t)
+{
+    constexpr int L = 2 * R + 1;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t z = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t y0 = (int64_t)blockIdx.y * (4 * P) + wave * P;
+    const int64_t xa = (int64_t)blockIdx.z * xchunk;
+    const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
+    const bool zl = z < nz;
+    const int64_t plane = ny * nz;
+    const float *col = T + (zl ? z : 0);
+    float *fcol = F + (zl ? z : 0);
+
+    float acc[P][L];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+        for (int m = 0; m < L; ++m) acc[q][m] = 0.0f;
+
+    const int64_t p_start = xa - R;
+    const int64_t p_end = xb - 1 + R;                       // inclusive
+    int64_t base = p_start >= 0 ? (p_start / L) * L : -(((-p_start) + L - 1) / L) * L;
+    for (int64_t p0 = base; p0 <= p_end; p0 += L) {
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const int64_t xp = p0 + j;                       // xp mod L == j
+            if (xp < p_start || xp > p_end) continue;
+            if (xp >= 0 && xp < nx && zl) {
+                float v[P + 2 * R];
+                const float *pl = col + xp * plane;
+#pragma unroll
+                for (int i = 0; i < P + 2 * R; ++i) {
+                    const int64_t yy = y0 - R + i;
+                    v[i] = (yy >= 0 && yy < ny) ? pl[yy * nz] : 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    float t2 = 0.0f;
+#pragma unroll
+                    for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], v[q + o], t2);
+#pragma unroll
+                    for (int k = 0; k < L; ++k) {
+                        const int slot = (j + R + 1 + k) % L;
+                        acc[q][slot] = fmaf(t.g[2 * R - k], t2, acc[q][slot]);
+                    }
+                }
+            }
+            const int slot_o = (j + R + 1) % L;
+            const int64_t xo = xp - R;
+            if (xo >= xa && xo < xb && zl) {
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    if (y0 + q < ny) fcol[xo * plane + (y0 + q) * nz] = acc[q][slot_o];
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) acc[q][slot_o] = 0.0f;
+        }
+    }
+}
+
+template <int R>
+hipError_t zpass_r(const float *in, float *out, Dims d, const Taps &tz, hipStream_t s)
+{
+    const dim3 grid((unsigned)(d.nx * d.ny), (unsigned)((d.nz + kZOut - 1) / kZOut));
+    prof::Scope scope("k_zpass_r", s);
+    hipLaunchKernelGGL(k_zpass_r<R>, grid, dim3(kThreads), 0, s, in, out, d.nz, tz);
+    return hipGetLastError();
+}
+
+template <int R, int P>
+hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, hipStream_t s)
+{
+    const int64_t tz = (d.nz + 63) / 64;
+    const int64_t ty = (d.ny + 4 * P - 1) / (4 * P);
+    // Split x so the grid has enough blocks to fill the chip; each chunk
+    // re-reads 2R planes of halo.
+    int64_t nxc = (1024 + tz * ty - 1) / (tz * ty);
+    const int64_t max_chunks = d.nx / (4 * (2 * R + 1)) > 0 ? d.nx / (4 * (2 * R + 1)) : 1;
+    if (nxc > max_chunks) nxc = max_chunks;
+    if (nxc < 1) nxc = 1;
+    const int64_t xchunk = (d.nx + nxc - 1) / nxc;
+    nxc = (d.nx + xchunk - 1) / xchunk;
+    const dim3 grid((unsigned)tz, (unsigned)ty, (unsigned)nxc);
+    prof::Scope scope("k_yx_r", s);
+    hipLaunchKernelGGL((k_yx_r<R, P>), grid, dim3(kThreads), 0, s, T, F, d.nx, d.ny, d.nz, xchunk,
+                       txy);
+    return hipGetLastError();
+}
+
+using ZFn = hipError_t (*)(const float *, float *, Dims, const Taps &, hipStream_t);
+using YXFn = hipError_t (*)(const float *, float *, Dims, const Taps &, hipStream_t);
+
+}  // namespace
+
+bool filter_fast_path(int rxy, int rz) { return rxy >= 1 && rxy <= kMaxFastRxy && rz >= 1 && rz <= kMaxFastRz; }
+
+hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
+                                const Taps &tz, hipStream_t s)
+{
+    static const ZFn ztab[kMaxFastRz + 1] = {
+        nullptr, &zpass_r<1>, &zpass_r<2>, &zpass_r<3>, &zpass_r<4>, &zpass_r<5>, &zpass_r<6>,
+        &zpass_r<7>, &zpass_r<8>, &zpass_r<9>, &zpass_r<10>, &zpass_r<11>, &zpass_r<12>,
+        &zpass_r<13>, &zpass_r<14>, &zpass_r<15>, &zpass_r<16>, &zpass_r<17>, &zpass_r<18>,
+        &zpass_r<19>, &zpass_r<20>, &zpass_r<21>, &zpass_r<22>, &zpass_r<23>, &zpass_r<24>,
+        &zpass_r<25>, &zpass_r<26>, &zpass_r<27>, &zpass_r<28>, &zpass_r<29>, &zpass_r<30>,
+        &zpass_r<31>, &zpass_r<32>};
+    static const YXFn yxtab[kMaxFastRxy + 1] = {
+        nullptr, &yx_r<1, 4>, &yx_r<2, 4>, &yx_r<3, 4>, &yx_r<4, 4>, &yx_r<5, 4>, &yx_r<6, 4>,
+        &yx_r<7, 4>, &yx_r<8, 4>, &yx_r<9, 4>, &yx_r<10, 4>, &yx_r<11, 4>, &yx_r<12, 4>,
+        &yx_r<13, 2>, &yx_r<14, 2>, &yx_r<15, 2>, &yx_r<16, 2>};
+    if (!filter_fast_path(txy.r, tz.r)) return hipErrorInvalidValue;
+    hipError_t e = ztab[tz.r](in, tmp, d, tz, s);
+    if (e != hipSuccess) return e;
+    return yxtab[txy.r](tmp, out, d, txy, s);
+}
+
+}  // namespace gsf

@@ -31,6 +31,28 @@ struct Box {
 // Number of per-block partial sums used for the global shift.
 constexpr int kShiftBlocks = 1024;
 
+// Kernel timing: a Scope records a start event on construction and a stop
+// event on destruction when profiling is enabled; kernels launched inside the
+// scope are what it times.
+namespace prof {
+bool enabled();
+struct Scope {
+    Scope(const char *name, hipStream_t s);
+    ~Scope();
+    int slot;
+    hipStream_t stream;
+};
+}  // namespace prof
+
+// Radii with compiled fast filter paths (gsf_filter.hip); larger radii use
+// the generic passes.
+constexpr int kMaxFastRz = 32;
+constexpr int kMaxFastRxy = 16;
+bool filter_fast_path(int rxy, int rz);
+// Spectral pass into tmp, then the fused y/x sweep into out.
+hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
+                                const Taps &tz, hipStream_t s);
+
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
 hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
                            const Taps &tz, hipStream_t s);

@@ -264,23 +264,39 @@ inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBloc
 hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
                            const Taps &tz, hipStream_t s)
 {
+    if (filter_fast_path(txy.r, tz.r)) return launch_filter3d_fast(in, out, tmp, d, txy, tz, s);
     const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
     // z: in -> out, y: out -> tmp, x: tmp -> out
-    hipLaunchKernelGGL(k_zpass, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s, in,
+    {
+        prof::Scope scope_("k_zpass", s);
+        hipLaunchKernelGGL(k_zpass, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s, in,
                        out, d.nz, tz);
-    hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)out, tmp, d.ny,
+    }
+    {
+        prof::Scope scope_("k_strided_pass", s);
+        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)out, tmp, d.ny,
                        d.nz, 0, d.ny, txy);
-    hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, out, d.ny,
+    }
+    {
+        prof::Scope scope_("k_strided_pass", s);
+        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, out, d.ny,
                        d.nz, 1, d.nx, txy);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_partial_sums, dim3(kShiftBlocks), dim3(kBlock), 0, s, F, d.voxels(),
+    {
+        prof::Scope scope_("k_partial_sums", s);
+        hipLaunchKernelGGL(k_partial_sums, dim3(kShiftBlocks), dim3(kBlock), 0, s, F, d.voxels(),
                        partials);
-    hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, (const double *)partials,
+    }
+    {
+        prof::Scope scope_("k_final_mean", s);
+        hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, (const double *)partials,
                        kShiftBlocks, d.voxels(), shift);
+    }
     return hipGetLastError();
 }
 
@@ -289,21 +305,33 @@ hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, floa
                         double k, hipStream_t s)
 {
     const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
-    hipLaunchKernelGGL(k_zbox, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), zlds, s,
+    {
+        prof::Scope scope_("k_zbox", s);
+        hipLaunchKernelGGL(k_zbox, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), zlds, s,
                        F, d.nz, b.bz, shift, ws1, ws2);
-    hipLaunchKernelGGL(k_ybox, dim3((unsigned)d.nx, ztiles(d.nz)), dim3(kBlock), 0, s,
+    }
+    {
+        prof::Scope scope_("k_ybox", s);
+        hipLaunchKernelGGL(k_ybox, dim3((unsigned)d.nx, ztiles(d.nz)), dim3(kBlock), 0, s,
                        (const float *)ws1, (const float *)ws2, ws3, ws4, d.ny, d.nz, b.by);
-    hipLaunchKernelGGL(k_xbox_final, dim3((unsigned)d.ny, ztiles(d.nz)), dim3(kBlock), 0, s,
+    }
+    {
+        prof::Scope scope_("k_xbox_final", s);
+        hipLaunchKernelGGL(k_xbox_final, dim3((unsigned)d.ny, ztiles(d.nz)), dim3(kBlock), 0, s,
                        (const float *)ws3, (const float *)ws4, F, d.nx, d.ny, d.nz, b, shift, mean,
                        stdev, mask, k);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_threshold(const float *F, const float *mean, const float *stdev, Dims d,
                             double k, uint64_t *mask, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_threshold, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), 0,
+    {
+        prof::Scope scope_("k_threshold", s);
+        hipLaunchKernelGGL(k_threshold, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), 0,
                        s, F, mean, stdev, d.nz, k, mask);
+    }
     return hipGetLastError();
 }
 
