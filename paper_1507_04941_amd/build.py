@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsf.so")
-SOURCES = ["gsf_api.cpp", "gsf_prof.cpp", "gsf_kernels.hip", "gsf_filter.hip"]
+SOURCES = ["gsf_api.cpp", "gsf_prof.cpp", "gsf_kernels.hip", "gsf_filter.hip", "gsf_stats.hip"]
 ARCH = "gfx950"
 
 

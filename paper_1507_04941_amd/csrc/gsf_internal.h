@@ -53,6 +53,13 @@ bool filter_fast_path(int rxy, int rz);
 hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
                                 const Taps &tz, hipStream_t s);
 
+// Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
+// bx in {8, 16, 32, 64}, bz <= 65.  ws G1, G2: two cubes of floats.
+bool stats_fast_path(Box b);
+hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,
+                             float *G2, float *mean, float *stdev, uint64_t *mask, double k,
+                             hipStream_t s);
+
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
 hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
                            const Taps &tz, hipStream_t s);

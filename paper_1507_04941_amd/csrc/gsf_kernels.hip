@@ -304,6 +304,8 @@ hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, floa
                         float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
                         double k, hipStream_t s)
 {
+    if (stats_fast_path(b))
+        return launch_stats_fast(F, d, b, shift, ws1, ws2, mean, stdev, mask, k, s);
     const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
     {
         prof::Scope scope_("k_zbox", s);

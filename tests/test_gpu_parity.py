@@ -71,6 +71,12 @@ def test_filter3d_impulse_is_sampled_kernel():
 
 STATS_CASES = [
     ((64, 64, 128), (32, 32, 32), 0.0),
+    ((70, 90, 200), (64, 32, 64), 0.0),   # fast path, ragged z strips
+    ((40, 80, 130), (32, 64, 16), 5.0),
+    ((33, 20, 129), (8, 16, 65), 0.0),   # widest z window the strip kernel takes
+    ((17, 9, 64), (16, 8, 1), 0.0),
+    ((5, 3, 70), (64, 64, 64), 0.0),     # box larger than every dim
+    ((12, 100, 7), (16, 64, 32), 0.0),
     ((20, 30, 200), (8, 6, 64), 0.0),
     ((9, 5, 70), (16, 16, 16), 0.0),   # box longer than x and y
     ((16, 16, 96), (5, 7, 9), 250.0),  # odd boxes, large offset (shift matters)
