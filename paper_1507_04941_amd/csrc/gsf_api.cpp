@@ -6,7 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "gsf_internal.h"
 
@@ -126,10 +128,11 @@ gsf::Box to_box(gsf_box b) { return gsf::Box{b.bx, b.by, b.bz}; }
 
 size_t cube_bytes(gsf_dims d) { return align_up((size_t)(d.nx * d.ny * d.nz) * sizeof(float)); }
 
-// Workspace pieces shared by the statistics schedule.
+// Workspace pieces shared by the statistics schedule: four scratch cubes,
+// the per-block partial sums of the shift and the shift itself.
 size_t stats_ws(gsf_dims d)
 {
-    return 4 * cube_bytes(d) + align_up(gsf::kShiftBlocks * sizeof(double)) +
+    return 4 * cube_bytes(d) + align_up(gsf::kMaxPartials * sizeof(double)) +
            align_up(sizeof(double));
 }
 
@@ -146,9 +149,16 @@ StatsWs carve_stats(char *p, gsf_dims d)
     w.w2 = (float *)p; p += c;
     w.w3 = (float *)p; p += c;
     w.w4 = (float *)p; p += c;
-    w.partials = (double *)p; p += align_up(gsf::kShiftBlocks * sizeof(double));
+    w.partials = (double *)p; p += align_up(gsf::kMaxPartials * sizeof(double));
     w.shift = (double *)p;
     return w;
+}
+
+// gsf_filter3d needs T1, plus a second scratch cube on the generic spatial path.
+size_t filter_ws(gsf_dims d, const gsf_filter *f)
+{
+    const int rxy = (int)std::ceil(f->truncate * f->sigma_xy);
+    return cube_bytes(d) * (gsf::yx_fast(rxy, to_dims(d)) ? 1 : 2);
 }
 
 gsf_status device_status(hipError_t e, const char *what)
@@ -190,7 +200,7 @@ gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *
     gsf_status st;
     if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
     if ((st = check_dims(d)) || (st = check_filter(f))) return st;
-    *bytes = cube_bytes(d);
+    *bytes = filter_ws(d, f);
     return ok();
 }
 
@@ -203,16 +213,20 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
         (st = check_dtype(out_t, "out_t")))
         return st;
     const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
-    const size_t need = cube_bytes(d);
+    const size_t need = filter_ws(d, f);
     if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((st = check_ptr(ws, 16, "ws"))) return st;
     if (overlaps(in, nb, out, nb) || overlaps(in, nb, ws, need) || overlaps(out, nb, ws, need))
         return fail(GSF_ERR_INVALID_ARG, "in, out and ws must not overlap");
     const gsf::Taps txy = make_taps(f->sigma_xy, f->truncate);
     const gsf::Taps tz = make_taps(f->sigma_z, f->truncate);
-    return device_status(gsf::launch_filter3d((const float *)in, (float *)out, (float *)ws,
-                                              to_dims(d), txy, tz, (hipStream_t)stream),
-                         "gsf_filter3d launch");
+    const gsf::Dims dd = to_dims(d);
+    const hipStream_t s = (hipStream_t)stream;
+    float *T1 = (float *)ws;
+    float *tmp = (float *)((char *)ws + cube_bytes(d));   // generic path only
+    hipError_t e = gsf::launch_zpass((const float *)in, T1, dd, tz, s);
+    if (e == hipSuccess) e = gsf::launch_yx(T1, (float *)out, tmp, dd, txy, nullptr, nullptr, s);
+    return device_status(e, "gsf_filter3d launch");
 }
 
 gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes)
@@ -295,7 +309,8 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
     return GSF_OK;
 }
 
-size_t find_ws(gsf_dims largest) { return stats_ws(largest) + cube_bytes(largest); }
+// [T1][F scratch][statistics workspace]
+size_t find_ws(gsf_dims largest) { return 2 * cube_bytes(largest) + stats_ws(largest); }
 
 }  // namespace
 
@@ -352,23 +367,40 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     }
     const hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
-    const StatsWs w = carve_stats(base, largest);
-    float *Fbuf = (float *)(base + stats_ws(largest));
+    float *T1 = (float *)base;
+    float *Fbuf = (float *)(base + cube_bytes(largest));
+    const StatsWs w = carve_stats(base + 2 * cube_bytes(largest), largest);
+    // The spectral pass depends only on (sigma_z, truncate): run it once per
+    // distinct pair and apply every filter that shares it.
+    std::vector<char> done((size_t)nfilt, 0);
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
         const gsf::Dims dd = to_dims(q.dims);
-        for (int32_t j = 0; j < nfilt; ++j) {
-            const int64_t o = (int64_t)c * nfilt + j;
-            float *F = (F_out && F_out[o]) ? (float *)F_out[o] : Fbuf;
-            const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
-            const gsf::Taps tz = make_taps(f[j].sigma_z, f[j].truncate);
-            hipError_t e = gsf::launch_filter3d((const float *)q.data, F, w.w1, dd, txy, tz, s);
-            if (e == hipSuccess) e = gsf::launch_mean(F, dd, w.partials, w.shift, s);
-            if (e == hipSuccess)
-                e = gsf::launch_stats(F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
-                                      mean_out ? mean_out[o] : nullptr,
-                                      std_out ? std_out[o] : nullptr, masks[o], k, s);
+        std::fill(done.begin(), done.end(), 0);
+        for (int32_t g = 0; g < nfilt; ++g) {
+            if (done[g]) continue;
+            const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
+            hipError_t e = gsf::launch_zpass((const float *)q.data, T1, dd, tz, s);
             if (e != hipSuccess) return device_status(e, "gsf_find launch");
+            for (int32_t j = g; j < nfilt; ++j) {
+                if (done[j] || f[j].sigma_z != f[g].sigma_z || f[j].truncate != f[g].truncate)
+                    continue;
+                done[j] = 1;
+                const int64_t o = (int64_t)c * nfilt + j;
+                float *F = (F_out && F_out[o]) ? (float *)F_out[o] : Fbuf;
+                const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
+                int nparts = 0;
+                e = gsf::launch_yx(T1, F, w.w1, dd, txy, w.partials, &nparts, s);
+                if (e == hipSuccess)
+                    e = nparts > 0 ? gsf::launch_mean_partials(w.partials, nparts, dd.voxels(),
+                                                               w.shift, s)
+                                   : gsf::launch_mean(F, dd, w.partials, w.shift, s);
+                if (e == hipSuccess)
+                    e = gsf::launch_stats(F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
+                                          mean_out ? mean_out[o] : nullptr,
+                                          std_out ? std_out[o] : nullptr, masks[o], k, s);
+                if (e != hipSuccess) return device_status(e, "gsf_find launch");
+            }
         }
     }
     return ok();

@@ -17,6 +17,7 @@
 // output sums its taps in ascending offset order, as in the definition.
 #include <hip/hip_runtime.h>
 
+#include "gsf_device.h"
 #include "gsf_internal.h"
 
 namespace gsf {
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ 
 template <int R, int P>
 __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
                                                    float *__restrict__ F, int64_t nx, int64_t ny,
-                                                   int64_t nz, int64_t xchunk, Taps t)
+                                                   int64_t nz, int64_t xchunk, Taps t,
+                                                   double *__restrict__ partials)
 {
     constexpr int L = 2 * R + 1;
     const int lane = threadIdx.x & 63;
@@ -81,8 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
     const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
     const bool zl = z < nz;
     const int64_t plane = ny * nz;
-    const float *col = T + (zl ? z : 0);
-    float *fcol = F + (zl ? z : 0);
+    const uint32_t plane_b = (uint32_t)(plane * 4);
+    const uint32_t row_b = (uint32_t)(nz * 4);
+    // byte offset of row y0 - R in a plane (wraps when negative: such rows
+    // read 0 through the buffer range check), and of row y0 for stores
+    const uint32_t ld0 = (uint32_t)(((y0 - R) * nz + z) * 4);
+    const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * 4) : kOOB;
 
     float acc[P][L];
 #pragma unroll
@@ -90,44 +96,78 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
 #pragma unroll
         for (int m = 0; m < L; ++m) acc[q][m] = 0.0f;
 
+    double fsum = 0.0;                                       // this lane's share of sum(F)
     const int64_t p_start = xa - R;
     const int64_t p_end = xb - 1 + R;                       // inclusive
     int64_t base = p_start >= 0 ? (p_start / L) * L : -(((-p_start) + L - 1) / L) * L;
+    // rows of the plane used at the next step, loaded one step ahead; planes
+    // outside [0, nx) contribute nothing
+    float v[P + 2 * R];
+    {
+        // a plane outside [0, nx) gets an empty range, so its loads read 0
+        const int64_t xq = base;
+        const bool in = xq >= 0 && xq < nx;
+        const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
+#pragma unroll
+        for (int i = 0; i < P + 2 * R; ++i) v[i] = buf_ld(rt, ld0 + (uint32_t)i * row_b);
+    }
+#pragma nounroll
     for (int64_t p0 = base; p0 <= p_end; p0 += L) {
 #pragma unroll
         for (int j = 0; j < L; ++j) {
+            // Every step of the rounded range runs: planes outside [0, nx)
+            // read 0 through an empty range and feed only outputs that are
+            // never written, so no branch encloses loads or accumulators.
             const int64_t xp = p0 + j;                       // xp mod L == j
-            if (xp < p_start || xp > p_end) continue;
-            if (xp >= 0 && xp < nx && zl) {
-                float v[P + 2 * R];
-                const float *pl = col + xp * plane;
+            float vn[P + 2 * R];
+            {
+                const int64_t xq = xp + 1;
+                const bool in = xq >= 0 && xq < nx;
+                const __amdgpu_buffer_rsrc_t rt =
+                    buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
 #pragma unroll
-                for (int i = 0; i < P + 2 * R; ++i) {
-                    const int64_t yy = y0 - R + i;
-                    v[i] = (yy >= 0 && yy < ny) ? pl[yy * nz] : 0.0f;
-                }
+                for (int i = 0; i < P + 2 * R; ++i) vn[i] = buf_ld(rt, ld0 + (uint32_t)i * row_b);
+            }
 #pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    float t2 = 0.0f;
+            for (int q = 0; q < P; ++q) {
+                float t2 = 0.0f;
 #pragma unroll
-                    for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], v[q + o], t2);
+                for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], v[q + o], t2);
 #pragma unroll
-                    for (int k = 0; k < L; ++k) {
-                        const int slot = (j + R + 1 + k) % L;
-                        acc[q][slot] = fmaf(t.g[2 * R - k], t2, acc[q][slot]);
-                    }
+                for (int k = 0; k < L; ++k) {
+                    const int slot = (j + R + 1 + k) % L;
+                    acc[q][slot] = fmaf(t.g[2 * R - k], t2, acc[q][slot]);
                 }
             }
             const int slot_o = (j + R + 1) % L;
             const int64_t xo = xp - R;
-            if (xo >= xa && xo < xb && zl) {
+            if (xo >= xa && xo < xb) {
+                const __amdgpu_buffer_rsrc_t rf = buf(F + xo * plane, plane_b);
 #pragma unroll
-                for (int q = 0; q < P; ++q)
-                    if (y0 + q < ny) fcol[xo * plane + (y0 + q) * nz] = acc[q][slot_o];
+                for (int q = 0; q < P; ++q) {
+                    buf_st(rf, acc[q][slot_o], st0 + (uint32_t)q * row_b);
+                    if (zl && y0 + q < ny) fsum += (double)acc[q][slot_o];
+                }
             }
 #pragma unroll
             for (int q = 0; q < P; ++q) acc[q][slot_o] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < P + 2 * R; ++i) v[i] = vn[i];
+            // one plane per step: look-ahead is the explicit one-plane prefetch
+            __builtin_amdgcn_sched_barrier(0);
         }
+    }
+    if (partials) {
+        // fixed-order block reduction of the lane sums (for the statistics' shift)
+        __shared__ double red[kThreads];
+        red[threadIdx.x] = fsum;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            partials[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
     }
 }
 
@@ -141,7 +181,8 @@ hipError_t zpass_r(const float *in, float *out, Dims d, const Taps &tz, hipStrea
 }
 
 template <int R, int P>
-hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, hipStream_t s)
+hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, double *partials, int *nparts,
+                hipStream_t s)
 {
     const int64_t tz = (d.nz + 63) / 64;
     const int64_t ty = (d.ny + 4 * P - 1) / (4 * P);
@@ -154,21 +195,26 @@ hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, hipStream_t s
     const int64_t xchunk = (d.nx + nxc - 1) / nxc;
     nxc = (d.nx + xchunk - 1) / xchunk;
     const dim3 grid((unsigned)tz, (unsigned)ty, (unsigned)nxc);
+    const int64_t blocks = tz * ty * nxc;
+    if (!partials || blocks > kMaxPartials) partials = nullptr;
+    if (nparts) *nparts = partials ? (int)blocks : 0;
     prof::Scope scope("k_yx_r", s);
     hipLaunchKernelGGL((k_yx_r<R, P>), grid, dim3(kThreads), 0, s, T, F, d.nx, d.ny, d.nz, xchunk,
-                       txy);
+                       txy, partials);
     return hipGetLastError();
 }
 
 using ZFn = hipError_t (*)(const float *, float *, Dims, const Taps &, hipStream_t);
-using YXFn = hipError_t (*)(const float *, float *, Dims, const Taps &, hipStream_t);
+using YXFn = hipError_t (*)(const float *, float *, Dims, const Taps &, double *, int *,
+                            hipStream_t);
 
 }  // namespace
 
-bool filter_fast_path(int rxy, int rz) { return rxy >= 1 && rxy <= kMaxFastRxy && rz >= 1 && rz <= kMaxFastRz; }
+bool zpass_fast(int rz) { return rz >= 1 && rz <= kMaxFastRz; }
+bool plane_fits(Dims d) { return d.ny * d.nz <= ((int64_t)1 << 28); }
+bool yx_fast(int rxy, Dims d) { return rxy >= 1 && rxy <= kMaxFastRxy && plane_fits(d); }
 
-hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
-                                const Taps &tz, hipStream_t s)
+hipError_t launch_zpass_fast(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s)
 {
     static const ZFn ztab[kMaxFastRz + 1] = {
         nullptr, &zpass_r<1>, &zpass_r<2>, &zpass_r<3>, &zpass_r<4>, &zpass_r<5>, &zpass_r<6>,
@@ -177,14 +223,21 @@ hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d,
         &zpass_r<19>, &zpass_r<20>, &zpass_r<21>, &zpass_r<22>, &zpass_r<23>, &zpass_r<24>,
         &zpass_r<25>, &zpass_r<26>, &zpass_r<27>, &zpass_r<28>, &zpass_r<29>, &zpass_r<30>,
         &zpass_r<31>, &zpass_r<32>};
+    if (!zpass_fast(tz.r)) return hipErrorInvalidValue;
+    return ztab[tz.r](in, T1, d, tz, s);
+}
+
+hipError_t launch_yx_fast(const float *T1, float *F, Dims d, const Taps &txy, double *partials,
+                          int *nparts, hipStream_t s)
+{
+    // rows per lane: 4 for short rings, fewer as the ring of 2R+1 partial
+    // sums per row grows, to keep at least two waves per SIMD
     static const YXFn yxtab[kMaxFastRxy + 1] = {
         nullptr, &yx_r<1, 4>, &yx_r<2, 4>, &yx_r<3, 4>, &yx_r<4, 4>, &yx_r<5, 4>, &yx_r<6, 4>,
-        &yx_r<7, 4>, &yx_r<8, 4>, &yx_r<9, 4>, &yx_r<10, 4>, &yx_r<11, 4>, &yx_r<12, 4>,
-        &yx_r<13, 2>, &yx_r<14, 2>, &yx_r<15, 2>, &yx_r<16, 2>};
-    if (!filter_fast_path(txy.r, tz.r)) return hipErrorInvalidValue;
-    hipError_t e = ztab[tz.r](in, tmp, d, tz, s);
-    if (e != hipSuccess) return e;
-    return yxtab[txy.r](tmp, out, d, txy, s);
+        &yx_r<7, 2>, &yx_r<8, 2>, &yx_r<9, 2>, &yx_r<10, 2>, &yx_r<11, 2>, &yx_r<12, 2>,
+        &yx_r<13, 1>, &yx_r<14, 1>, &yx_r<15, 1>, &yx_r<16, 1>};
+    if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
+    return yxtab[txy.r](T1, F, d, txy, partials, nparts, s);
 }
 
 }  // namespace gsf

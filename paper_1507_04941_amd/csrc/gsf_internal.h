@@ -44,29 +44,42 @@ struct Scope {
 };
 }  // namespace prof
 
+// Per-block FP64 partial sums of F for the statistics' shift.
+constexpr int kMaxPartials = 1 << 16;
+
 // Radii with compiled fast filter paths (gsf_filter.hip); larger radii use
 // the generic passes.
 constexpr int kMaxFastRz = 32;
 constexpr int kMaxFastRxy = 16;
-bool filter_fast_path(int rxy, int rz);
-// Spectral pass into tmp, then the fused y/x sweep into out.
-hipError_t launch_filter3d_fast(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
-                                const Taps &tz, hipStream_t s);
+bool zpass_fast(int rz);
+// Buffer-addressed kernels need one x-plane below 2^30 bytes.
+bool plane_fits(Dims d);
+bool yx_fast(int rxy, Dims d);
+hipError_t launch_zpass_fast(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s);
+hipError_t launch_yx_fast(const float *T1, float *F, Dims d, const Taps &txy, double *partials,
+                          int *nparts, hipStream_t s);
 
 // Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
 // bx in {8, 16, 32, 64}, bz <= 65.  ws G1, G2: two cubes of floats.
-bool stats_fast_path(Box b);
+bool stats_fast_path(Box b, Dims d);
 hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,
                              float *G2, float *mean, float *stdev, uint64_t *mask, double k,
                              hipStream_t s);
 
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
-hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
-                           const Taps &tz, hipStream_t s);
-// shift[0] = mean of F (FP64), computed with a fixed reduction order.
+// Spectral pass: T1 = gz * in along z.
+hipError_t launch_zpass(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s);
+// Spatial passes: F = gxy * (gxy * T1 along y) along x.  tmp is a scratch
+// cube used only by the generic path.  If partials is non-null, per-block
+// FP64 sums of F may be written there; *nparts gets their count (0 if not).
+hipError_t launch_yx(const float *T1, float *F, float *tmp, Dims d, const Taps &txy,
+                     double *partials, int *nparts, hipStream_t s);
+// shift[0] = mean of F (FP64), full pass over F with a fixed reduction order.
 hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s);
-// Local statistics and (optionally) the mask in one schedule.
-// ws1..ws4: four scratch cubes of d.voxels() floats.
+// shift[0] = (sum of n partials) / V, fixed order.
+hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double *shift,
+                                hipStream_t s);
+// Local statistics and (optionally) the mask.  ws1..ws4: four scratch cubes.
 hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, float *ws1, float *ws2,
                         float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
                         double k, hipStream_t s);

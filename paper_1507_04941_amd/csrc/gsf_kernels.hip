@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_xbox_final(
             double var = s2 / n - m1 * m1;
             if (var < 0.0) var = 0.0;
             const float mf = (float)(s + m1);
-            const float sf = (float)sqrt(var);
+            const float sf = sqrtf((float)var);
             const int64_t i = x * plane + base;
             if (mean) mean[i] = mf;
             if (stdev) stdev[i] = sf;
@@ -261,26 +261,43 @@ inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_filter3d(const float *in, float *out, float *tmp, Dims d, const Taps &txy,
-                           const Taps &tz, hipStream_t s)
+hipError_t launch_zpass(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s)
 {
-    if (filter_fast_path(txy.r, tz.r)) return launch_filter3d_fast(in, out, tmp, d, txy, tz, s);
+    if (zpass_fast(tz.r)) return launch_zpass_fast(in, T1, d, tz, s);
     const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
-    // z: in -> out, y: out -> tmp, x: tmp -> out
     {
         prof::Scope scope_("k_zpass", s);
         hipLaunchKernelGGL(k_zpass, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s, in,
-                       out, d.nz, tz);
+                           T1, d.nz, tz);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_yx(const float *T1, float *F, float *tmp, Dims d, const Taps &txy,
+                     double *partials, int *nparts, hipStream_t s)
+{
+    if (yx_fast(txy.r, d)) return launch_yx_fast(T1, F, d, txy, partials, nparts, s);
+    if (nparts) *nparts = 0;
+    const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
+    {
+        prof::Scope scope_("k_strided_pass", s);
+        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, T1, tmp, d.ny, d.nz, 0, d.ny,
+                           txy);
     }
     {
         prof::Scope scope_("k_strided_pass", s);
-        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)out, tmp, d.ny,
-                       d.nz, 0, d.ny, txy);
+        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, F, d.ny,
+                           d.nz, 1, d.nx, txy);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double *shift,
+                                hipStream_t s)
+{
     {
-        prof::Scope scope_("k_strided_pass", s);
-        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, out, d.ny,
-                       d.nz, 1, d.nx, txy);
+        prof::Scope scope_("k_final_mean", s);
+        hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, partials, n, V, shift);
     }
     return hipGetLastError();
 }
@@ -304,7 +321,7 @@ hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, floa
                         float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
                         double k, hipStream_t s)
 {
-    if (stats_fast_path(b))
+    if (stats_fast_path(b, d))
         return launch_stats_fast(F, d, b, shift, ws1, ws2, mean, stdev, mask, k, s);
     const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
     {

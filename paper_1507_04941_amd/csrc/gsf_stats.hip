@@ -15,6 +15,7 @@
 // window sum is exact to well below FP32 rounding before it is stored.
 #include <hip/hip_runtime.h>
 
+#include "gsf_device.h"
 #include "gsf_internal.h"
 
 namespace gsf {
@@ -79,16 +80,18 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
 }
 
 // z window of one row for the 64 outputs of a wave.  Lane i carries the
-// column sums c(i) and c(i + 64) of the strip plus its window; output i is
-// H(i) = P(i + bz - 1) - P(i - 1) with P the inclusive prefix over the 128
-// columns.  P is FP64, so the difference keeps FP64 accuracy relative to the
-// strip's largest prefix and H is exact to well below FP32 rounding.
-__device__ __forceinline__ float zwin(double lo, double hi, double *q, int lane, int bz)
+// column sums u = c(2i) and v = c(2i + 1) of the strip plus its window; the
+// output of lane i is H(i) = P(i + bz - 1) - P(i - 1), P the inclusive prefix
+// over the 128 columns.  P is FP64 (one wave scan of the lane pair sums), so
+// the difference keeps FP64 accuracy relative to the strip's largest prefix
+// and H is exact to well below FP32 rounding.
+__device__ __forceinline__ float zwin(double u, double v, double *q, int lane, int bz)
 {
-    const double plo = wave_incl_scan_d(lo);
-    const double phi = wave_incl_scan_d(hi) + readlane_d(plo, 63);
-    q[lane] = plo;
-    q[lane + 64] = phi;
+    const double pair = u + v;
+    const double incl = wave_incl_scan_d(pair);
+    const double excl = incl - pair;
+    q[2 * lane] = excl + u;
+    q[2 * lane + 1] = incl;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const double h = q[lane + bz - 1] - (lane > 0 ? q[lane - 1] : 0.0);
@@ -97,17 +100,7 @@ __device__ __forceinline__ float zwin(double lo, double hi, double *q, int lane,
     return (float)h;
 }
 
-__device__ __forceinline__ void emit_row(double a1, double a2, double b1, double b2, double *q1,
-                                         double *q2, int lane, int bz, bool live, float *g1,
-                                         float *g2)
-{
-    const float h1 = zwin(a1, b1, q1, lane, bz);
-    const float h2 = zwin(a2, b2, q2, lane, bz);
-    if (live) {
-        *g1 = h1;
-        *g2 = h2;
-    }
-}
+constexpr int kAhead = 4;   // loads issued this many steps before use
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
@@ -118,6 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
                                                      float *__restrict__ G1,
                                                      float *__restrict__ G2)
 {
+    static_assert(BY % kAhead == 0, "ring length must be a multiple of the prefetch depth");
     __shared__ double qs[4][2][128];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -130,46 +124,85 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
     const int loy = -(BY / 2);
     const int hiy = loy + BY - 1;
     const float s = (float)shift[0];
-    // the two columns this lane carries: c = lane and c = lane + 64
-    const int64_t zc0 = z0 + loz + lane;
-    const int64_t zc1 = zc0 + 64;
-    const bool v0 = zc0 >= 0 && zc0 < nz;
-    const bool v1 = (lane + 64 < 64 + bz - 1) && zc1 >= 0 && zc1 < nz;
-    const float *pl = F + x * ny * nz;
+    const int64_t plane = ny * nz;
+    const uint32_t plane_b = (uint32_t)(plane * 4);
+    const uint32_t row_b = (uint32_t)(nz * 4);
+    // the two adjacent columns this lane carries: t = 2*lane and 2*lane + 1
+    const int64_t zc0 = z0 + loz + 2 * lane;
+    const int64_t zc1 = zc0 + 1;
+    const bool v0 = (2 * lane < 64 + bz - 1) && zc0 >= 0 && zc0 < nz;
+    const bool v1 = (2 * lane + 1 < 64 + bz - 1) && zc1 >= 0 && zc1 < nz;
+    const uint32_t o0 = v0 ? (uint32_t)(zc0 * 4) : kOOB;
+    const uint32_t o1 = v1 ? (uint32_t)(zc1 * 4) : kOOB;
+    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, plane_b);
     const int64_t zo = z0 + lane;
+    const uint32_t og = zo < nz ? (uint32_t)(zo * 4) : kOOB;
+    const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
+    const __amdgpu_buffer_rsrc_t rg2 = buf(G2 + x * plane, plane_b);
     float ring0[BY], ring1[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ring0[j] = ring1[j] = 0.0f;
-    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums, columns 0 and 1
+    // rows kAhead steps ahead; rows past the cube and dead columns load 0
+    float pf0[kAhead], pf1[kAhead];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+        pf0[j] = buf_ld(rf, o0 + (uint32_t)j * row_b);
+        pf1[j] = buf_ld(rf, o1 + (uint32_t)j * row_b);
+    }
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of the two columns
     double *q1 = qs[wave][0];
     double *q2 = qs[wave][1];
-    const int64_t nsteps = ny + hiy;                  // entering rows 0 .. ny-1+hiy
+    // entering rows 0 .. ny-1+hiy, rounded up to whole rings: surplus steps
+    // read rows past the cube (0) and emit nothing.  No branch encloses the
+    // loads or the ring, so prefetched values are never copied before use.
+    const int64_t nsteps = ny + hiy;
+#pragma nounroll
     for (int64_t y0 = 0; y0 < nsteps; y0 += BY) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < BY; ++j) {
             const int64_t yin = y0 + j;                   // yin mod BY == j
-            if (yin < nsteps) {
-                float e0 = 0.0f, e1 = 0.0f;
-                if (yin < ny) {
-                    if (v0) e0 = pl[yin * nz + zc0] - s;
-                    if (v1) e1 = pl[yin * nz + zc1] - s;
-                }
-                const float l0 = ring0[j], l1 = ring1[j];
-                ring0[j] = e0;
-                ring1[j] = e1;
-                a1 += (double)e0 - (double)l0;
-                a2 += (double)(e0 * e0) - (double)(l0 * l0);
-                b1 += (double)e1 - (double)l1;
-                b2 += (double)(e1 * e1) - (double)(l1 * l1);
-                const int64_t y = yin - hiy;
-                if (y >= 0) emit_row(a1, a2, b1, b2, q1, q2, lane, bz, zo < nz,
-                                     G1 + (x * ny + y) * nz + zo, G2 + (x * ny + y) * nz + zo);
+            const bool row = yin < ny;
+            const float e0 = (row && v0) ? pf0[j % kAhead] - s : 0.0f;
+            const float e1 = (row && v1) ? pf1[j % kAhead] - s : 0.0f;
+            const uint32_t ra = (uint32_t)(yin + kAhead) * row_b;   // past ny: outside the plane
+            pf0[j % kAhead] = buf_ld(rf, o0 + ra);
+            pf1[j % kAhead] = buf_ld(rf, o1 + ra);
+            const float l0 = ring0[j], l1 = ring1[j];
+            ring0[j] = e0;
+            ring1[j] = e1;
+            a1 += (double)e0 - (double)l0;
+            a2 += (double)(e0 * e0) - (double)(l0 * l0);
+            b1 += (double)e1 - (double)l1;
+            b2 += (double)(e1 * e1) - (double)(l1 * l1);
+            const int64_t y = yin - hiy;
+            if (y >= 0 && y < ny) {
+                const float h1 = zwin(a1, b1, q1, lane, bz);
+                const float h2 = zwin(a2, b2, q2, lane, bz);
+                const uint32_t oy = og + (uint32_t)y * row_b;
+                buf_st(rg1, h1, oy);
+                buf_st(rg2, h2, oy);
             }
+            // look-ahead comes from the explicit prefetch, not from hoisting
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-// One lane per (y, z), 256 consecutive z per block; walks x.
+// 1/c for window lengths c = 0..64 (entry 0 unused).
+__constant__ double kInv[65] = {
+    0.0,       1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,
+    1.0 / 9,   1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17,
+    1.0 / 18,  1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26,
+    1.0 / 27,  1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33, 1.0 / 34, 1.0 / 35,
+    1.0 / 36,  1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44,
+    1.0 / 45,  1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53,
+    1.0 / 54,  1.0 / 55, 1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62,
+    1.0 / 63,  1.0 / 64};
+
+// One lane per (y, z), 256 consecutive z per block; walks x.  Per step the
+// lane loads the entering plane's G1, G2 and the output plane's F (issued
+// kAhead steps early), updates the FP64 window sums with the ring of the
+// last BX planes, and finishes the output plane.
 template <int BX>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const float *__restrict__ G1, const float *__restrict__ G2, const float *__restrict__ F,
@@ -177,60 +210,81 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
 #pragma clang fp contract(off)
+    static_assert(BX % kAhead == 0 && BX <= 64, "ring length");
     const int64_t y = blockIdx.y;
-    const int64_t zb = (int64_t)blockIdx.x * kThreads;
-    const int64_t z = zb + threadIdx.x;
+    const int64_t z = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool live = z < nz;
     const int64_t plane = ny * nz;
-    const int64_t off = y * nz + (live ? z : 0);
+    const uint32_t plane_b = (uint32_t)(plane * 4);
+    // offset of (y, z) inside a plane; dead lanes address outside every plane
+    const uint32_t off = live ? (uint32_t)((y * nz + z) * 4) : kOOB;
     const int64_t W = (nz + 63) / 64;
-    const int lox = -(BX / 2);
-    const int hix = lox + BX - 1;
+    const int hix = -(BX / 2) + BX - 1;
     const double s = (double)(float)shift[0];   // the same FP32 shift the sums used
-    const double inv_yz = live ? 1.0 / (double)(win_len(y, ny, by) * win_len(z, nz, bz)) : 1.0;
-    const double inv_bx = 1.0 / (double)BX;
+    const double inv_yz =
+        live ? 1.0 / (double)(win_len(y, ny, by) * win_len(z, nz, bz)) : 1.0;
+    uint64_t *mrow = mask ? mask + y * W + z / 64 : nullptr;   // + x*ny*W per plane
+    const int64_t mstride = ny * W;
     float r1[BX], r2[BX];
 #pragma unroll
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
+    // loads issued kAhead steps early: plane pa of G (entering) and plane
+    // pa - hix of F (output); a plane outside [0, nx) has an empty range
+    float pg1[kAhead], pg2[kAhead], pfv[kAhead];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+        const bool in = j < nx;
+        const int64_t xf = j - hix;
+        const bool fin = xf >= 0 && xf < nx;
+        pg1[j] = buf_ld(buf(G1 + j * plane, in ? plane_b : 0u), off);
+        pg2[j] = buf_ld(buf(G2 + j * plane, in ? plane_b : 0u), off);
+        pfv[j] = buf_ld(buf(F + xf * plane, fin ? plane_b : 0u), off);
+    }
     double s1 = 0.0, s2 = 0.0;
+    // entering planes 0 .. nx-1+hix, rounded up to whole rings: surplus steps
+    // load empty ranges and emit nothing; only the output part is branched
     const int64_t nsteps = nx + hix;
+    const float *g1p = G1 + kAhead * plane, *g2p = G2 + kAhead * plane;
+    const float *fp = F + (kAhead - hix) * plane;
+#pragma nounroll
     for (int64_t p0 = 0; p0 < nsteps; p0 += BX) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
             const int64_t p = p0 + j;                         // entering plane, p mod BX == j
-            if (p < nsteps) {
-                float g1 = 0.0f, g2 = 0.0f;
-                if (p < nx && live) {
-                    g1 = G1[p * plane + off];
-                    g2 = G2[p * plane + off];
-                }
-                s1 += (double)g1 - (double)r1[j];
-                s2 += (double)g2 - (double)r2[j];
-                r1[j] = g1;
-                r2[j] = g2;
-                const int64_t x = p - hix;
-                if (x >= 0) {
-                    bool bit = false;
-                    if (live) {
-                        const int64_t cx = win_len(x, nx, BX);
-                        const double inv_n = inv_yz * (cx == BX ? inv_bx : 1.0 / (double)cx);
-                        const double m1 = s1 * inv_n;
-                        double var = s2 * inv_n - m1 * m1;
-                        if (var < 0.0) var = 0.0;
-                        const float mf = (float)(s + m1);
-                        const float sf = (float)sqrt(var);
-                        const int64_t i = x * plane + off;
-                        if (mean) mean[i] = mf;
-                        if (stdev) stdev[i] = sf;
-                        if (mask) bit = (double)F[i] > (double)mf + k * (double)sf;
-                    }
-                    if (mask) {
-                        const uint64_t word = __ballot(bit);
-                        if ((threadIdx.x & 63) == 0 && live)
-                            mask[(x * ny + y) * W + z / 64] = word;
-                    }
+            const float g1 = pg1[j % kAhead], g2 = pg2[j % kAhead];
+            const float fv = pfv[j % kAhead];
+            const int64_t pa = p + kAhead;
+            const int64_t xf = pa - hix;
+            const uint32_t nin = pa < nx ? plane_b : 0u;
+            const uint32_t nfv = (xf >= 0 && xf < nx) ? plane_b : 0u;
+            pg1[j % kAhead] = buf_ld(buf(g1p, nin), off);
+            pg2[j % kAhead] = buf_ld(buf(g2p, nin), off);
+            pfv[j % kAhead] = buf_ld(buf(fp, nfv), off);
+            g1p += plane;
+            g2p += plane;
+            fp += plane;
+            s1 += (double)g1 - (double)r1[j];
+            s2 += (double)g2 - (double)r2[j];
+            r1[j] = g1;
+            r2[j] = g2;
+            const int64_t x = p - hix;
+            if (x >= 0 && x < nx) {
+                // n = cx * cy * cz, cx the clipped window length along x
+                const double inv_n = inv_yz * kInv[win_len(x, nx, BX)];
+                const double m1 = s1 * inv_n;
+                double var = s2 * inv_n - m1 * m1;
+                var = var < 0.0 ? 0.0 : var;
+                const float mf = (float)(s + m1);
+                const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
+                if (mean) buf_st(buf(mean + x * plane, plane_b), mf, off);
+                if (stdev) buf_st(buf(stdev + x * plane, plane_b), sf, off);
+                if (mrow) {
+                    const bool bit = live && (double)fv > (double)mf + k * (double)sf;
+                    const uint64_t word = __ballot(bit);
+                    if ((threadIdx.x & 63) == 0 && live) mrow[x * mstride] = word;
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -287,13 +341,16 @@ XFn x_fn(int bx)
 
 }  // namespace
 
-bool stats_fast_path(Box b) { return yz_fn(b.by) && x_fn(b.bx) && b.bz >= 1 && b.bz <= 65; }
+bool stats_fast_path(Box b, Dims d)
+{
+    return yz_fn(b.by) && x_fn(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d);
+}
 
 hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,
                              float *G2, float *mean, float *stdev, uint64_t *mask, double k,
                              hipStream_t s)
 {
-    if (!stats_fast_path(b)) return hipErrorInvalidValue;
+    if (!stats_fast_path(b, d)) return hipErrorInvalidValue;
     hipError_t e = yz_fn(b.by)(F, d, b.bz, shift, G1, G2, s);
     if (e != hipSuccess) return e;
     return x_fn(b.bx)(G1, G2, F, d, b, shift, mean, stdev, mask, k, s);
