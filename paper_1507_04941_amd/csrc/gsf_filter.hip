@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
 {
     constexpr int L = 2 * R + 1;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t z = (int64_t)blockIdx.x * 64 + lane;
     const int64_t y0 = (int64_t)blockIdx.y * (4 * P) + wave * P;
     const int64_t xa = (int64_t)blockIdx.z * xchunk;

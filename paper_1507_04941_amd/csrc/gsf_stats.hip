@@ -100,7 +100,8 @@ __device__ __forceinline__ float zwin(double u, double v, double *q, int lane, i
     return (float)h;
 }
 
-constexpr int kAhead = 4;   // loads issued this many steps before use
+constexpr int kAhead = 4;    // rows the y walk loads before use
+constexpr int kAheadX = 8;   // planes the x walk loads before use (it is latency-bound)
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
@@ -114,7 +115,9 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
     static_assert(BY % kAhead == 0, "ring length must be a multiple of the prefetch depth");
     __shared__ double qs[4][2][128];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform by construction; readfirstlane lets the compiler keep the
+    // plane's buffer descriptors in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nstrips = (nz + 63) / 64;
     const int64_t job = (int64_t)blockIdx.x * 4 + wave;
     if (job >= nx * nstrips) return;                 // whole wave exits together
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
 #pragma clang fp contract(off)
-    static_assert(BX % kAhead == 0 && BX <= 64, "ring length");
+    static_assert(BX % kAheadX == 0 && BX <= 64, "ring length");
     const int64_t y = blockIdx.y;
     const int64_t z = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool live = z < nz;
@@ -228,11 +231,11 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     float r1[BX], r2[BX];
 #pragma unroll
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
-    // loads issued kAhead steps early: plane pa of G (entering) and plane
+    // loads issued kAheadX steps early: plane pa of G (entering) and plane
     // pa - hix of F (output); a plane outside [0, nx) has an empty range
-    float pg1[kAhead], pg2[kAhead], pfv[kAhead];
+    float pg1[kAheadX], pg2[kAheadX], pfv[kAheadX];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
+    for (int j = 0; j < kAheadX; ++j) {
         const bool in = j < nx;
         const int64_t xf = j - hix;
         const bool fin = xf >= 0 && xf < nx;
@@ -244,22 +247,22 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     // entering planes 0 .. nx-1+hix, rounded up to whole rings: surplus steps
     // load empty ranges and emit nothing; only the output part is branched
     const int64_t nsteps = nx + hix;
-    const float *g1p = G1 + kAhead * plane, *g2p = G2 + kAhead * plane;
-    const float *fp = F + (kAhead - hix) * plane;
+    const float *g1p = G1 + kAheadX * plane, *g2p = G2 + kAheadX * plane;
+    const float *fp = F + (kAheadX - hix) * plane;
 #pragma nounroll
     for (int64_t p0 = 0; p0 < nsteps; p0 += BX) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
             const int64_t p = p0 + j;                         // entering plane, p mod BX == j
-            const float g1 = pg1[j % kAhead], g2 = pg2[j % kAhead];
-            const float fv = pfv[j % kAhead];
-            const int64_t pa = p + kAhead;
+            const float g1 = pg1[j % kAheadX], g2 = pg2[j % kAheadX];
+            const float fv = pfv[j % kAheadX];
+            const int64_t pa = p + kAheadX;
             const int64_t xf = pa - hix;
             const uint32_t nin = pa < nx ? plane_b : 0u;
             const uint32_t nfv = (xf >= 0 && xf < nx) ? plane_b : 0u;
-            pg1[j % kAhead] = buf_ld(buf(g1p, nin), off);
-            pg2[j % kAhead] = buf_ld(buf(g2p, nin), off);
-            pfv[j % kAhead] = buf_ld(buf(fp, nfv), off);
+            pg1[j % kAheadX] = buf_ld(buf(g1p, nin), off);
+            pg2[j % kAheadX] = buf_ld(buf(g2p, nin), off);
+            pfv[j % kAheadX] = buf_ld(buf(fp, nfv), off);
             g1p += plane;
             g2p += plane;
             fp += plane;
