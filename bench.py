@@ -45,14 +45,19 @@ def algorithmic_bytes(kernel: str, V: int) -> float | None:
     """Bytes one launch of `kernel` must move for a V-voxel FP32 cube: each
     input read once and each output written once (masks are V/8 bytes)."""
     table = {
-        "k_zpass": 8.0 * V,            # read d, write T1
+        "k_zpass_r": 8.0 * V,          # read d, write T1
+        "k_yx_r": 8.0 * V,             # read T1, write F
+        "k_zpass": 8.0 * V,
         "k_strided_pass": 8.0 * V,     # read T, write T'
         "k_partial_sums": 4.0 * V,     # read F
+        "k_box_yz": 12.0 * V,          # read F, write G1, G2
+        "k_box_x_select": 12.0 * V + V / 8.0,   # read G1, G2, F, write mask
         "k_zbox": 12.0 * V,            # read F, write Z1, Z2
         "k_ybox": 16.0 * V,            # read Z1, Z2, write Y1, Y2
         "k_xbox_final": 12.0 * V + V / 8.0,   # read Y1, Y2, F, write mask
         "k_threshold": 12.0 * V + V / 8.0,
     }
+    kernel = kernel.split("<")[0]
     return table.get(kernel)
 
 

@@ -6,8 +6,8 @@
 //     segment with its +-R halo in LDS using coalesced loads; every lane then
 //     holds a (4 + 2R)-wide window in registers (ds_read_b128) and produces 4
 //     consecutive outputs, so each staged value feeds up to 4(2R+1) FMAs.
-//   k_yx_r<R, P>: F = gxy * (gxy * T1 along y) along x.  A block owns a 64-wide
-//     z strip (one lane per z, coalesced rows) and 4 waves x P rows of y, and
+//   k_yx_r<R, P, NW>: F = gxy * (gxy * T1 along y) along x.  A block owns a
+//     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of y, and
 //     sweeps an x range plane by plane.  For each plane it forms the y-pass of
 //     its P points from 2R + P row loads, then scatters that value into a
 //     register ring of 2R+1 partial x sums per point; the oldest sum is
@@ -68,8 +68,8 @@ __global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ 
     }
 }
 
-template <int R, int P>
-__global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
+template <int R, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
                                                    float *__restrict__ F, int64_t nx, int64_t ny,
                                                    int64_t nz, int64_t xchunk, Taps t,
                                                    double *__restrict__ partials)
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t z = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t y0 = (int64_t)blockIdx.y * (4 * P) + wave * P;
+    const int64_t y0 = (int64_t)blockIdx.y * (NW * P) + wave * P;
     const int64_t xa = (int64_t)blockIdx.z * xchunk;
     const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
     const bool zl = z < nz;
@@ -159,10 +159,10 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
     }
     if (partials) {
         // fixed-order block reduction of the lane sums (for the statistics' shift)
-        __shared__ double red[kThreads];
+        __shared__ double red[64 * NW];
         red[threadIdx.x] = fsum;
         __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
+        for (int w = 32 * NW; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
@@ -171,24 +171,38 @@ __global__ __launch_bounds__(kThreads) void k_yx_r(const float *__restrict__ T,
     }
 }
 
+// Timing names per radius (the profile aggregates launches by name).
+const char *const kZNames[] = {
+    "k_zpass_r<0>",  "k_zpass_r<1>",  "k_zpass_r<2>",  "k_zpass_r<3>",  "k_zpass_r<4>",
+    "k_zpass_r<5>",  "k_zpass_r<6>",  "k_zpass_r<7>",  "k_zpass_r<8>",  "k_zpass_r<9>",
+    "k_zpass_r<10>", "k_zpass_r<11>", "k_zpass_r<12>", "k_zpass_r<13>", "k_zpass_r<14>",
+    "k_zpass_r<15>", "k_zpass_r<16>", "k_zpass_r<17>", "k_zpass_r<18>", "k_zpass_r<19>",
+    "k_zpass_r<20>", "k_zpass_r<21>", "k_zpass_r<22>", "k_zpass_r<23>", "k_zpass_r<24>",
+    "k_zpass_r<25>", "k_zpass_r<26>", "k_zpass_r<27>", "k_zpass_r<28>", "k_zpass_r<29>",
+    "k_zpass_r<30>", "k_zpass_r<31>", "k_zpass_r<32>"};
+const char *const kYxNames[] = {
+    "k_yx_r<0>",  "k_yx_r<1>",  "k_yx_r<2>",  "k_yx_r<3>",  "k_yx_r<4>",  "k_yx_r<5>",
+    "k_yx_r<6>",  "k_yx_r<7>",  "k_yx_r<8>",  "k_yx_r<9>",  "k_yx_r<10>", "k_yx_r<11>",
+    "k_yx_r<12>", "k_yx_r<13>", "k_yx_r<14>", "k_yx_r<15>", "k_yx_r<16>"};
+
 template <int R>
 hipError_t zpass_r(const float *in, float *out, Dims d, const Taps &tz, hipStream_t s)
 {
     const dim3 grid((unsigned)(d.nx * d.ny), (unsigned)((d.nz + kZOut - 1) / kZOut));
-    prof::Scope scope("k_zpass_r", s);
+    prof::Scope scope(kZNames[R], s);
     hipLaunchKernelGGL(k_zpass_r<R>, grid, dim3(kThreads), 0, s, in, out, d.nz, tz);
     return hipGetLastError();
 }
 
-template <int R, int P>
+template <int R, int P, int NW>
 hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, double *partials, int *nparts,
                 hipStream_t s)
 {
     const int64_t tz = (d.nz + 63) / 64;
-    const int64_t ty = (d.ny + 4 * P - 1) / (4 * P);
+    const int64_t ty = (d.ny + NW * P - 1) / (NW * P);
     // Split x so the grid has enough blocks to fill the chip; each chunk
     // re-reads 2R planes of halo.
-    int64_t nxc = (1024 + tz * ty - 1) / (tz * ty);
+    int64_t nxc = (512 + tz * ty - 1) / (tz * ty);
     const int64_t max_chunks = d.nx / (4 * (2 * R + 1)) > 0 ? d.nx / (4 * (2 * R + 1)) : 1;
     if (nxc > max_chunks) nxc = max_chunks;
     if (nxc < 1) nxc = 1;
@@ -198,9 +212,9 @@ hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, double *parti
     const int64_t blocks = tz * ty * nxc;
     if (!partials || blocks > kMaxPartials) partials = nullptr;
     if (nparts) *nparts = partials ? (int)blocks : 0;
-    prof::Scope scope("k_yx_r", s);
-    hipLaunchKernelGGL((k_yx_r<R, P>), grid, dim3(kThreads), 0, s, T, F, d.nx, d.ny, d.nz, xchunk,
-                       txy, partials);
+    prof::Scope scope(kYxNames[R], s);
+    hipLaunchKernelGGL((k_yx_r<R, P, NW>), grid, dim3(64 * NW), 0, s, T, F, d.nx, d.ny, d.nz,
+                       xchunk, txy, partials);
     return hipGetLastError();
 }
 
@@ -230,12 +244,15 @@ hipError_t launch_zpass_fast(const float *in, float *T1, Dims d, const Taps &tz,
 hipError_t launch_yx_fast(const float *T1, float *F, Dims d, const Taps &txy, double *partials,
                           int *nparts, hipStream_t s)
 {
-    // rows per lane: 4 for short rings, fewer as the ring of 2R+1 partial
-    // sums per row grows, to keep at least two waves per SIMD
+    // 8 waves per block so a block's y tile (8 waves x P rows) is tall enough
+    // to amortise the 2R halo rows it re-reads: blocks sweeping x drift apart,
+    // so halo rows are not shared through L2 across blocks.  P shrinks as the
+    // ring of 2R+1 partial sums per row grows (at most 256 VGPRs per lane).
     static const YXFn yxtab[kMaxFastRxy + 1] = {
-        nullptr, &yx_r<1, 4>, &yx_r<2, 4>, &yx_r<3, 4>, &yx_r<4, 4>, &yx_r<5, 4>, &yx_r<6, 4>,
-        &yx_r<7, 2>, &yx_r<8, 2>, &yx_r<9, 2>, &yx_r<10, 2>, &yx_r<11, 2>, &yx_r<12, 2>,
-        &yx_r<13, 1>, &yx_r<14, 1>, &yx_r<15, 1>, &yx_r<16, 1>};
+        nullptr, &yx_r<1, 4, 8>, &yx_r<2, 4, 8>, &yx_r<3, 4, 8>, &yx_r<4, 4, 8>, &yx_r<5, 4, 8>,
+        &yx_r<6, 4, 8>, &yx_r<7, 3, 8>, &yx_r<8, 3, 8>, &yx_r<9, 3, 8>, &yx_r<10, 3, 8>,
+        &yx_r<11, 3, 8>, &yx_r<12, 3, 8>, &yx_r<13, 1, 8>, &yx_r<14, 1, 8>, &yx_r<15, 1, 8>,
+        &yx_r<16, 1, 8>};
     if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
     return yxtab[txy.r](T1, F, d, txy, partials, nparts, s);
 }

@@ -297,7 +297,7 @@ hipError_t box_yz(const float *F, Dims d, int bz, const double *shift, float *G1
                   hipStream_t s)
 {
     const int64_t jobs = d.nx * ((d.nz + 63) / 64);
-    prof::Scope scope("k_box_yz", s);
+    prof::Scope scope(BY == 64 ? "k_box_yz<64>" : BY == 32 ? "k_box_yz<32>" : BY == 16 ? "k_box_yz<16>" : "k_box_yz<8>", s);
     hipLaunchKernelGGL(k_box_yz<BY>, dim3((unsigned)((jobs + 3) / 4)), dim3(kThreads), 0, s, F,
                        d.nx, d.ny, d.nz, bz, shift, G1, G2);
     return hipGetLastError();
@@ -309,7 +309,7 @@ hipError_t box_x_select(const float *G1, const float *G2, const float *F, Dims d
                         hipStream_t s)
 {
     const dim3 grid((unsigned)((d.nz + kThreads - 1) / kThreads), (unsigned)d.ny);
-    prof::Scope scope("k_box_x_select", s);
+    prof::Scope scope(BX == 64 ? "k_box_x_select<64>" : BX == 32 ? "k_box_x_select<32>" : BX == 16 ? "k_box_x_select<16>" : "k_box_x_select<8>", s);
     hipLaunchKernelGGL(k_box_x_select<BX>, grid, dim3(kThreads), 0, s, G1, G2, F, d.nx, d.ny, d.nz,
                        b.by, b.bz, shift, mean, stdev, mask, k);
     return hipGetLastError();
