@@ -7,12 +7,14 @@
 //     holds a (4 + 2R)-wide window in registers (ds_read_b128) and produces 4
 //     consecutive outputs, so each staged value feeds up to 4(2R+1) FMAs.
 //   k_yx_r<R, P, NW>: F = gxy * (gxy * T1 along y) along x.  A block owns a
-//     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of y, and
-//     sweeps an x range plane by plane.  For each plane it forms the y-pass of
-//     its P points from 2R + P row loads, then scatters that value into a
-//     register ring of 2R+1 partial x sums per point; the oldest sum is
-//     complete and written after every plane.  T1 is read once and F written
-//     once; nothing else touches memory.
+//     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of
+//     y, and sweeps an x range plane by plane.  The block's waves load each
+//     plane's NW*P + 2R rows once, cooperatively, two planes ahead, into a
+//     three-stage LDS ring (one barrier per plane); each lane then forms the
+//     y pass of its P points from LDS and scatters it into a register ring of
+//     2R+1 partial x sums per point; the oldest sum is complete and written
+//     after every plane.  T1 is read once (plus the 2R halo rows per block)
+//     and F written once.
 // Taps are compile-time indexed kernel arguments (scalar registers).  Every
 // output sums its taps in ascending offset order, as in the definition.
 #include <hip/hip_runtime.h>
@@ -70,24 +72,35 @@ __global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ 
 
 template <int R, int P, int NW>
 __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
-                                                   float *__restrict__ F, int64_t nx, int64_t ny,
-                                                   int64_t nz, int64_t xchunk, Taps t,
-                                                   double *__restrict__ partials)
+                                                  float *__restrict__ F, int64_t nx, int64_t ny,
+                                                  int64_t nz, int64_t xchunk, Taps t,
+                                                  double *__restrict__ partials)
 {
     constexpr int L = 2 * R + 1;
+    constexpr int TY = NW * P;            // output rows of the block
+    constexpr int TR = TY + 2 * R;        // rows of T1 one plane of the block needs
+    constexpr int LW = (TR + NW - 1) / NW;   // rows each wave loads per plane
+    constexpr int S = 3;                  // LDS stages: read xp, written xp+1, retired xp-1
+    __shared__ float stage[S][TR][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int64_t z = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t y0 = (int64_t)blockIdx.y * (NW * P) + wave * P;
+    const int64_t yb = (int64_t)blockIdx.y * TY;                   // first output row of the block
+    const int64_t y0 = yb + wave * P;                              // this wave's first row
     const int64_t xa = (int64_t)blockIdx.z * xchunk;
     const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
     const bool zl = z < nz;
     const int64_t plane = ny * nz;
     const uint32_t plane_b = (uint32_t)(plane * 4);
     const uint32_t row_b = (uint32_t)(nz * 4);
-    // byte offset of row y0 - R in a plane (wraps when negative: such rows
-    // read 0 through the buffer range check), and of row y0 for stores
-    const uint32_t ld0 = (uint32_t)(((y0 - R) * nz + z) * 4);
+    // rows w, w + NW, ... of the block's TR-row window are this wave's to load;
+    // offsets wrap for rows above the cube and read 0 through the range check
+    uint32_t ldo[LW];
+#pragma unroll
+    for (int i = 0; i < LW; ++i) {
+        const int tr = wave + i * NW;
+        ldo[i] = tr < TR ? (uint32_t)(((yb - R + tr) * nz + z) * 4) : kOOB;
+    }
     const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * 4) : kOOB;
 
     float acc[P][L];
@@ -100,39 +113,49 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
     const int64_t p_start = xa - R;
     const int64_t p_end = xb - 1 + R;                       // inclusive
     int64_t base = p_start >= 0 ? (p_start / L) * L : -(((-p_start) + L - 1) / L) * L;
-    // rows of the plane used at the next step, loaded one step ahead; planes
-    // outside [0, nx) contribute nothing
-    float v[P + 2 * R];
-    {
-        // a plane outside [0, nx) gets an empty range, so its loads read 0
-        const int64_t xq = base;
+
+    // a plane outside [0, nx) gets an empty range, so its rows read 0
+    auto load_plane = [&](int64_t xq, float (&r)[LW]) {
         const bool in = xq >= 0 && xq < nx;
         const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
 #pragma unroll
-        for (int i = 0; i < P + 2 * R; ++i) v[i] = buf_ld(rt, ld0 + (uint32_t)i * row_b);
-    }
+        for (int i = 0; i < LW; ++i) r[i] = buf_ld(rt, ldo[i]);
+    };
+    auto store_stage = [&](int st, const float (&r)[LW]) {
+#pragma unroll
+        for (int i = 0; i < LW; ++i) {
+            const int tr = wave + i * NW;
+            if (tr < TR) stage[st][tr][lane] = r[i];
+        }
+    };
+    // prologue: plane base in LDS, planes base+1 and base+2 in registers.
+    // Each step writes plane xp+1 to its stage and issues the loads of plane
+    // xp+3, so a load has two planes of compute to arrive.
+    float ra[LW], rb[LW];
+    load_plane(base, ra);
+    store_stage(base % S < 0 ? base % S + S : base % S, ra);
+    load_plane(base + 1, ra);
+    load_plane(base + 2, rb);
+    int64_t sx = ((base % S) + S) % S;                      // stage holding plane xp
+
 #pragma nounroll
     for (int64_t p0 = base; p0 <= p_end; p0 += L) {
 #pragma unroll
         for (int j = 0; j < L; ++j) {
             // Every step of the rounded range runs: planes outside [0, nx)
-            // read 0 through an empty range and feed only outputs that are
-            // never written, so no branch encloses loads or accumulators.
+            // read 0 and feed only outputs that are never written.
             const int64_t xp = p0 + j;                       // xp mod L == j
-            float vn[P + 2 * R];
-            {
-                const int64_t xq = xp + 1;
-                const bool in = xq >= 0 && xq < nx;
-                const __amdgpu_buffer_rsrc_t rt =
-                    buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
+            const int s1 = (int)(sx + 1 >= S ? sx + 1 - S : sx + 1);
+            store_stage(s1, ra);                             // plane xp+1
 #pragma unroll
-                for (int i = 0; i < P + 2 * R; ++i) vn[i] = buf_ld(rt, ld0 + (uint32_t)i * row_b);
-            }
+            for (int i = 0; i < LW; ++i) ra[i] = rb[i];      // plane xp+2 moves up
+            load_plane(xp + 3, rb);                          // plane xp+3
+            __syncthreads();                                 // plane xp complete; plane xp-1 retired
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 float t2 = 0.0f;
 #pragma unroll
-                for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], v[q + o], t2);
+                for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], stage[sx][wave * P + q + o][lane], t2);
 #pragma unroll
                 for (int k = 0; k < L; ++k) {
                     const int slot = (j + R + 1 + k) % L;
@@ -151,9 +174,7 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
             }
 #pragma unroll
             for (int q = 0; q < P; ++q) acc[q][slot_o] = 0.0f;
-#pragma unroll
-            for (int i = 0; i < P + 2 * R; ++i) v[i] = vn[i];
-            // one plane per step: look-ahead is the explicit one-plane prefetch
+            sx = s1;
             __builtin_amdgcn_sched_barrier(0);
         }
     }
