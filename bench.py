@@ -30,7 +30,8 @@ METRIC = ("GVoxel-filters/s + % HBM roofline (FP32 vs FP16-storage); p50/p99 sub
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_04941_amd", "csrc", n)
-                  for n in ("gsf_kernels.hip", "gsf_api.cpp", "gsf_internal.h")]
+                  for n in ("gsf_kernels.hip", "gsf_filter.hip", "gsf_stats.hip",
+                            "gsf_device.h", "gsf_internal.h", "gsf_api.cpp")]
 
 
 def kernel_source_sha() -> str:
@@ -61,11 +62,16 @@ def algorithmic_bytes(kernel: str, V: int) -> float | None:
     return table.get(kernel)
 
 
+def traffic_file(kernel: str, workload: str) -> str:
+    tag = kernel.replace("<", "_").replace(">", "").replace(",", "_")
+    return os.path.join(PROFILES, f"{tag}_{workload}_traffic.txt")
+
+
 def read_traffic(kernel: str, workload: str, sha: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when there is none for this kernel/workload or the kernel sources
     changed since it was taken."""
-    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.txt")
+    path = traffic_file(kernel, workload)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -130,7 +136,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["large", "small"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",

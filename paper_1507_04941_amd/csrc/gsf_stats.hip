@@ -101,7 +101,7 @@ __device__ __forceinline__ float zwin(double u, double v, double *q, int lane, i
 }
 
 constexpr int kAhead = 4;    // rows the y walk loads before use
-constexpr int kAheadX = 8;   // planes the x walk loads before use (it is latency-bound)
+constexpr int kAheadX = 4;   // planes the x walk loads before use
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
