@@ -52,6 +52,7 @@ def algorithmic_bytes(kernel: str, V: int) -> float | None:
         "k_strided_pass": 8.0 * V,     # read T, write T'
         "k_partial_sums": 4.0 * V,     # read F
         "k_box_yz": 12.0 * V,          # read F, write G1, G2
+        "k_box_yz_seg": 12.0 * V,
         "k_box_x_select": 12.0 * V + V / 8.0,   # read G1, G2, F, write mask
         "k_zbox": 12.0 * V,            # read F, write Z1, Z2
         "k_ybox": 16.0 * V,            # read Z1, Z2, write Y1, Y2

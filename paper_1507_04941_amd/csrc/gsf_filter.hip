@@ -6,6 +6,9 @@
 //     segment with its +-R halo in LDS using coalesced loads; every lane then
 //     holds a (4 + 2R)-wide window in registers (ds_read_b128) and produces 4
 //     consecutive outputs, so each staged value feeds up to 4(2R+1) FMAs.
+//   k_zpass_rows<R>: the same for rows of a multiple of 4 values, with a
+//     block walking 16 rows, 16-byte row loads one row ahead of use and a
+//     double-buffered tile.
 //   k_yx_r<R, P, NW>: F = gxy * (gxy * T1 along y) along x.  A block owns a
 //     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of
 //     y, and sweeps an x range plane by plane.  The block's waves load each
@@ -67,6 +70,72 @@ __global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ 
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (z + k < nz) dst[k] = acc[k];
+    }
+}
+
+// The same spectral pass for rows whose length is a multiple of 4 (so every
+// row starts 16-byte aligned): a block walks kZRows consecutive rows of one
+// 1024-wide z chunk, loading each row with 16-byte loads one row ahead of
+// its use into a double-buffered LDS tile (one barrier per row).
+constexpr int kZRows = 16;
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_zpass_rows(const float *__restrict__ in,
+                                                         float *__restrict__ out, int64_t nrows,
+                                                         int64_t nz, Taps t)
+{
+    constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
+    constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
+    __shared__ float4 tile4[2][TL / 4];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kZRows;
+    const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
+    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    const int64_t zm = z0 + 4 * tid;                 // this lane's four values and outputs
+    const bool mine = zm < nz;                       // nz % 4 == 0: all four or none
+    // halo: lanes 0 .. 2R-1 fetch z0 - R + lane (left) and z0 + kZOut + lane - R (right)
+    const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
+    const bool halo = tid < 2 * R && zh >= 0 && zh < nz;
+    const int th = tid < R ? tid : kZOut + tid;      // its tile index
+    float4 m = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float h = 0.0f;
+    {
+        const float *row = in + r0 * nz;
+        if (mine) m = *reinterpret_cast<const float4 *>(row + zm);
+        if (halo) h = row[zh];
+    }
+    for (int64_t r = r0; r < r1; ++r) {
+        const int b = (int)((r - r0) & 1);
+        float *tile = reinterpret_cast<float *>(tile4[b]);
+        tile[R + 4 * tid] = m.x;
+        tile[R + 4 * tid + 1] = m.y;
+        tile[R + 4 * tid + 2] = m.z;
+        tile[R + 4 * tid + 3] = m.w;
+        if (tid < 2 * R) tile[th] = h;
+        __syncthreads();
+        if (r + 1 < r1) {
+            const float *row = in + (r + 1) * nz;
+            m = mine ? *reinterpret_cast<const float4 *>(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
+            h = halo ? row[zh] : 0.0f;
+        }
+        float w[4 * NW];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const float4 q = tile4[b][tid + j];
+            w[4 * j] = q.x;
+            w[4 * j + 1] = q.y;
+            w[4 * j + 2] = q.z;
+            w[4 * j + 3] = q.w;
+        }
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int o = 0; o <= 2 * R; ++o) {
+            const float g = t.g[o];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
+        }
+        if (mine)
+            *reinterpret_cast<float4 *>(out + r * nz + zm) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
 }
 
@@ -209,9 +278,16 @@ const char *const kYxNames[] = {
 template <int R>
 hipError_t zpass_r(const float *in, float *out, Dims d, const Taps &tz, hipStream_t s)
 {
-    const dim3 grid((unsigned)(d.nx * d.ny), (unsigned)((d.nz + kZOut - 1) / kZOut));
+    const int64_t rows = d.nx * d.ny;
+    const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     prof::Scope scope(kZNames[R], s);
-    hipLaunchKernelGGL(k_zpass_r<R>, grid, dim3(kThreads), 0, s, in, out, d.nz, tz);
+    if (d.nz % 4 == 0) {
+        const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
+        hipLaunchKernelGGL(k_zpass_rows<R>, grid, dim3(kThreads), 0, s, in, out, rows, d.nz, tz);
+    } else {
+        hipLaunchKernelGGL(k_zpass_r<R>, dim3((unsigned)rows, zt), dim3(kThreads), 0, s, in, out,
+                           d.nz, tz);
+    }
     return hipGetLastError();
 }
 

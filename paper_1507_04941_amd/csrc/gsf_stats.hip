@@ -2,17 +2,20 @@
 //
 // The window sums of a = F - s and a^2 over the box around each voxel are
 // computed as directional sums in two kernels:
-//   k_box_yz<BY>: for one x-plane and a 64-wide z strip per wave, walk y with
-//     a running window sum per column (the value leaving the window comes
-//     from a register ring of the last BY rows, so F is read once), then take
-//     the z window across lanes with wave-wide DPP prefix sums.  Writes the
-//     yz-window sums G1 = sum a, G2 = sum a^2 for every voxel.
+//   k_box_yz_seg<BY,BZ> (z window BZ = 16, 32, 64) and k_box_yz<BY> (any
+//     z window up to 65): for one x-plane and a 64-wide z strip per wave,
+//     walk y with a running window sum per column (the value leaving the
+//     window comes from a register ring of the last BY rows, so F is read
+//     once), then take the z window across lanes with DPP lane scans.
+//     Writes the yz-window sums G1 = sum a, G2 = sum a^2 for every voxel.
 //   k_box_x_select<BX>: one lane per (y, z) walks x with a running window sum
 //     of G1, G2 (leaving plane from a register ring of the last BX planes),
 //     then forms mean = s + S1/n and std = sqrt(max(0, S2/n - (S1/n)^2)),
 //     and the selection bit F > mean + k*std, packed along z by wave ballot.
-// Running sums and the lane prefix sums of the z window are FP64, so every
-// window sum is exact to well below FP32 rounding before it is stored.
+// Running sums are FP64.  The z window is either an FP32 sum of a segment
+// tail and the next segment's head (power-of-two windows: no subtraction, so
+// it is accurate relative to itself) or a difference of FP64 lane prefix
+// sums (any window).
 #include <hip/hip_runtime.h>
 
 #include "gsf_device.h"
@@ -23,23 +26,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// ---- wave64 inclusive prefix sum with DPP (row shifts, then row broadcasts) ----
+// ---- lane shifts through DPP ----
 template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_ZERO>
 __device__ __forceinline__ float dpp_f(float v)
 {
     return __int_as_float(
         __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO));
-}
-
-__device__ __forceinline__ float wave_incl_scan(float v)
-{
-    v += dpp_f<0x111, 0xf, 0xf, true>(v);   // row_shr:1
-    v += dpp_f<0x112, 0xf, 0xf, true>(v);   // row_shr:2
-    v += dpp_f<0x114, 0xf, 0xf, true>(v);   // row_shr:4
-    v += dpp_f<0x118, 0xf, 0xf, true>(v);   // row_shr:8
-    v += dpp_f<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
 }
 
 __device__ __forceinline__ int64_t win_len(int64_t i, int64_t n, int B)
@@ -71,12 +63,6 @@ __device__ __forceinline__ double wave_incl_scan_d(double v)
     v += dpp_d<0x142, 0xa, 0xf, false>(v);
     v += dpp_d<0x143, 0xc, 0xf, false>(v);
     return v;
-}
-
-__device__ __forceinline__ double readlane_d(double v, int lane)
-{
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                            __builtin_amdgcn_readlane(__double2loint(v), lane));
 }
 
 // z window of one row for the 64 outputs of a wave.  Lane i carries the
@@ -191,6 +177,153 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
     }
 }
 
+// Inclusive prefix sums inside each group of BZ consecutive lanes (BZ = 16,
+// 32 or 64) of four independent values, level by level so that no DPP read
+// waits on the add just before it.  Row shifts stop at 16-lane rows; the row
+// broadcasts join rows (lane 15 into rows 1 and 3, then lane 31 into rows 2
+// and 3).  A broadcast add leaves the rows outside its row mask unchanged,
+// which the compiler's DPP builtins can only express with an extra zeroed
+// register and a separate add, so those two levels are written as one DPP
+// add each; the leading s_nop provides the wait states a DPP read needs
+// after the VALU write of its source.
+template <int CTRL>
+__device__ __forceinline__ void shr_level(float (&v)[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] += dpp_f<CTRL, 0xf, 0xf, true>(v[i]);
+}
+
+__device__ __forceinline__ void bcast15_level(float (&v)[4])
+{
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_bcast:15 row_mask:0xa bank_mask:0xf"
+        : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+
+__device__ __forceinline__ void bcast31_level(float (&v)[4])
+{
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+
+template <int BZ>
+__device__ __forceinline__ void seg_scan4(float (&v)[4])
+{
+    shr_level<0x111>(v);   // row_shr:1
+    shr_level<0x112>(v);   // row_shr:2
+    shr_level<0x114>(v);   // row_shr:4
+    shr_level<0x118>(v);   // row_shr:8
+    if constexpr (BZ >= 32) bcast15_level(v);
+    if constexpr (BZ >= 64) bcast31_level(v);
+}
+
+// The same job as k_box_yz for a power-of-two z window BZ, with the z window
+// built from sums that never subtract: the strip's columns are cut into
+// segments of BZ, and the window of output z is the tail of one segment plus
+// the head of the next.  Lane i (segment j = i / BZ, position q = i % BZ)
+// carries column A = start of segment j + BZ-1-q and column B = start of
+// segment j+1 + q.  After the y walk, an inclusive scan of the A values
+// inside each BZ-lane group gives at lane i the tail of segment j from
+// BZ-1-q, and a scan of the B values gives heads of segment j+1; lane i
+// therefore finishes output column j*BZ + BZ-1-q, adding the head of length
+// BZ-1-q fetched from lane j*BZ + BZ-2-q.  Column sums along y are FP64
+// running sums of FP32 increments, rounded once to FP32 before the scans; a
+// scan only adds same-window partial sums, so each window sum is accurate
+// relative to itself.
+template <int BY, int BZ>
+__global__ __launch_bounds__(kThreads) void k_box_yz_seg(const float *__restrict__ F, int64_t nx,
+                                                         int64_t ny64, int64_t nz64,
+                                                         const double *__restrict__ shift,
+                                                         float *__restrict__ G1,
+                                                         float *__restrict__ G2)
+{
+#pragma clang fp contract(off)
+    static_assert(BY % kAhead == 0, "ring length must be a multiple of the prefetch depth");
+    static_assert(BZ == 16 || BZ == 32 || BZ == 64, "segment length");
+    // a plane holds at most 2^28 voxels, so in-plane indices fit 32 bits
+    const int ny = (int)ny64, nz = (int)nz64;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nstrips = (nz + 63) / 64;
+    const int64_t job = (int64_t)blockIdx.x * 4 + wave;
+    if (job >= nx * nstrips) return;                 // whole wave exits together
+    const int64_t x = job / nstrips;
+    const int z0 = (int)(job % nstrips) * 64;
+    const int hiy = -(BY / 2) + BY - 1;
+    const float s = (float)shift[0];
+    const int64_t plane = (int64_t)ny * nz;
+    const uint32_t plane_b = (uint32_t)(plane * 4);
+    const uint32_t row_b = (uint32_t)nz * 4u;
+    const int seg = lane / BZ, q = lane % BZ;
+    const int za = z0 - BZ / 2 + seg * BZ + (BZ - 1 - q);
+    const int zb = z0 - BZ / 2 + (seg + 1) * BZ + q;
+    const bool va = za >= 0 && za < nz;
+    const bool vb = zb >= 0 && zb < nz;
+    const uint32_t oa = va ? (uint32_t)za * 4u : kOOB;
+    const uint32_t ob = vb ? (uint32_t)zb * 4u : kOOB;
+    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, plane_b);
+    // output column of this lane and the lane holding the head it adds
+    const int zo = z0 + seg * BZ + (BZ - 1 - q);
+    const uint32_t og = zo < nz ? (uint32_t)zo * 4u : kOOB;
+    const bool has_head = q < BZ - 1;
+    const int src = has_head ? seg * BZ + (BZ - 2 - q) : lane;
+    const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
+    const __amdgpu_buffer_rsrc_t rg2 = buf(G2 + x * plane, plane_b);
+    float ringa[BY], ringb[BY];
+#pragma unroll
+    for (int j = 0; j < BY; ++j) ringa[j] = ringb[j] = 0.0f;
+    float pfa[kAhead], pfb[kAhead];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+        pfa[j] = buf_ld(rf, oa + (uint32_t)j * row_b);
+        pfb[j] = buf_ld(rf, ob + (uint32_t)j * row_b);
+    }
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of columns A and B
+    const int nsteps = ny + hiy;
+#pragma nounroll
+    for (int y0 = 0; y0 < nsteps; y0 += BY) {
+#pragma clang loop unroll(full)
+        for (int j = 0; j < BY; ++j) {
+            const int yin = y0 + j;                       // yin mod BY == j
+            const bool row = yin < ny;
+            const float ea = (row && va) ? pfa[j % kAhead] - s : 0.0f;
+            const float eb = (row && vb) ? pfb[j % kAhead] - s : 0.0f;
+            const uint32_t ra = (uint32_t)(yin + kAhead) * row_b;   // past ny: outside the plane
+            pfa[j % kAhead] = buf_ld(rf, oa + ra);
+            pfb[j % kAhead] = buf_ld(rf, ob + ra);
+            const float la = ringa[j], lb = ringb[j];
+            ringa[j] = ea;
+            ringb[j] = eb;
+            a1 += (double)(ea - la);
+            a2 += (double)(ea * ea - la * la);
+            b1 += (double)(eb - lb);
+            b2 += (double)(eb * eb - lb * lb);
+            const int y = yin - hiy;
+            if (y >= 0 && y < ny) {
+                float t[4] = {(float)a1, (float)a2, (float)b1, (float)b2};
+                seg_scan4<BZ>(t);
+                const float h1 = __int_as_float(
+                    __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
+                const float h2 = __int_as_float(
+                    __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
+                const uint32_t oy = og + (uint32_t)y * row_b;
+                buf_st(rg1, has_head ? t[0] + h1 : t[0], oy);
+                buf_st(rg2, has_head ? t[1] + h2 : t[1], oy);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 // 1/c for window lengths c = 0..64 (entry 0 unused).
 __constant__ double kInv[65] = {
     0.0,       1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,
@@ -202,89 +335,138 @@ __constant__ double kInv[65] = {
     1.0 / 54,  1.0 / 55, 1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62,
     1.0 / 63,  1.0 / 64};
 
+__device__ __forceinline__ int win_len32(int i, int n, int B)
+{
+    int lo = i - (B / 2);
+    int hi = lo + B;
+    if (lo < 0) lo = 0;
+    if (hi > n) hi = n;
+    return hi - lo;
+}
+
+// A copy of a uniform value the compiler cannot see through: offsets built
+// from it each ring turn are recomputed per step instead of being hoisted
+// out of the loop into dozens of live registers.
+__device__ __forceinline__ uint32_t opaque(uint32_t v)
+{
+    uint32_t r;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+    return r;
+}
+
+// Buffer descriptor over planes [p, p + span) of a cube with nx planes,
+// clipped to the cube (empty when p >= nx).  Loads and stores address a
+// plane inside it with (plane - p) * plane bytes added to the lane's 32-bit
+// offset (the range-checked one); a plane past the clip lies outside the
+// range and reads 0 / drops the store.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const float *c, int p, int span,
+                                                             int nx, uint32_t plane_b)
+{
+    const int n = p < nx ? (nx - p < span ? nx - p : span) : 0;
+    const int pc = p < nx ? p : nx;
+    return buf(c + (int64_t)pc * (plane_b / 4), (uint32_t)n * plane_b);
+}
+
 // One lane per (y, z), 256 consecutive z per block; walks x.  Per step the
 // lane loads the entering plane's G1, G2 and the output plane's F (issued
-// kAhead steps early), updates the FP64 window sums with the ring of the
-// last BX planes, and finishes the output plane.
+// kAheadX steps early), updates the FP64 window sums with the ring of the
+// last BX planes, and finishes the output plane.  Plane addressing is
+// 32-bit: every BX steps the kernel sets up descriptors over the next BX
+// planes of each stream and steps through them with scalar offsets, which
+// needs BX + 1 planes to span less than 2^31 bytes.
 template <int BX>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const float *__restrict__ G1, const float *__restrict__ G2, const float *__restrict__ F,
-    int64_t nx, int64_t ny, int64_t nz, int by, int bz, const double *__restrict__ shift,
+    int64_t nx64, int64_t ny64, int64_t nz64, int by, int bz, const double *__restrict__ shift,
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
 #pragma clang fp contract(off)
     static_assert(BX % kAheadX == 0 && BX <= 64, "ring length");
-    const int64_t y = blockIdx.y;
-    const int64_t z = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int nx = (int)nx64, ny = (int)ny64, nz = (int)nz64;
+    const int y = blockIdx.y;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int z = blockIdx.x * kThreads + threadIdx.x;
     const bool live = z < nz;
-    const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);
-    // offset of (y, z) inside a plane; dead lanes address outside every plane
-    const uint32_t off = live ? (uint32_t)((y * nz + z) * 4) : kOOB;
-    const int64_t W = (nz + 63) / 64;
+    const uint32_t plane_b = (uint32_t)ny * (uint32_t)nz * 4u;
+    // offset of (y, z) inside a plane; dead lanes address outside every range
+    const uint32_t off = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * 4u : kOOB;
+    const int W = (nz + 63) / 64;
     const int hix = -(BX / 2) + BX - 1;
     const double s = (double)(float)shift[0];   // the same FP32 shift the sums used
     const double inv_yz =
         live ? 1.0 / (double)(win_len(y, ny, by) * win_len(z, nz, bz)) : 1.0;
-    uint64_t *mrow = mask ? mask + y * W + z / 64 : nullptr;   // + x*ny*W per plane
-    const int64_t mstride = ny * W;
+    const int64_t mstride = (int64_t)ny * W;
+    // this wave's mask word of plane 0 (wave-uniform); plane x adds x * mstride
+    uint64_t *mrow = mask ? mask + (int64_t)y * W + blockIdx.x * (kThreads / 64) + wave : nullptr;
     float r1[BX], r2[BX];
 #pragma unroll
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
     // loads issued kAheadX steps early: plane pa of G (entering) and plane
-    // pa - hix of F (output); a plane outside [0, nx) has an empty range
+    // pa - hix of F (output)
     float pg1[kAheadX], pg2[kAheadX], pfv[kAheadX];
+    {
+        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, kAheadX, nx, plane_b);
+        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, kAheadX, nx, plane_b);
+        const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, kAheadX, nx, plane_b);
 #pragma unroll
-    for (int j = 0; j < kAheadX; ++j) {
-        const bool in = j < nx;
-        const int64_t xf = j - hix;
-        const bool fin = xf >= 0 && xf < nx;
-        pg1[j] = buf_ld(buf(G1 + j * plane, in ? plane_b : 0u), off);
-        pg2[j] = buf_ld(buf(G2 + j * plane, in ? plane_b : 0u), off);
-        pfv[j] = buf_ld(buf(F + xf * plane, fin ? plane_b : 0u), off);
+        for (int j = 0; j < kAheadX; ++j) {
+            const int xf = j - hix;
+            pg1[j] = buf_ld(q1, off + (uint32_t)j * plane_b);
+            pg2[j] = buf_ld(q2, off + (uint32_t)j * plane_b);
+            pfv[j] = buf_ld(qf, off + (uint32_t)(xf >= 0 ? xf : BX) * plane_b);
+        }
     }
     double s1 = 0.0, s2 = 0.0;
     // entering planes 0 .. nx-1+hix, rounded up to whole rings: surplus steps
     // load empty ranges and emit nothing; only the output part is branched
-    const int64_t nsteps = nx + hix;
-    const float *g1p = G1 + kAheadX * plane, *g2p = G2 + kAheadX * plane;
-    const float *fp = F + (kAheadX - hix) * plane;
+    const int nsteps = nx + hix;
 #pragma nounroll
-    for (int64_t p0 = 0; p0 < nsteps; p0 += BX) {
+    for (int p0 = 0; p0 < nsteps; p0 += BX) {
+        // planes loaded in this ring turn: G planes ga + j, F planes fa + j;
+        // output planes xo + j (j < BX).  A plane offset of BX planes is
+        // outside every span.
+        const int ga = p0 + kAheadX;
+        const int fa = ga - hix;
+        const int fb = fa > 0 ? fa : 0;
+        const int xo = p0 - hix;
+        const int xb = xo > 0 ? xo : 0;
+        const uint32_t pb = opaque(plane_b);
+        const __amdgpu_buffer_rsrc_t rg1 = plane_span(G1, ga, BX, nx, plane_b);
+        const __amdgpu_buffer_rsrc_t rg2 = plane_span(G2, ga, BX, nx, plane_b);
+        const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane_b);
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
-            const int64_t p = p0 + j;                         // entering plane, p mod BX == j
             const float g1 = pg1[j % kAheadX], g2 = pg2[j % kAheadX];
             const float fv = pfv[j % kAheadX];
-            const int64_t pa = p + kAheadX;
-            const int64_t xf = pa - hix;
-            const uint32_t nin = pa < nx ? plane_b : 0u;
-            const uint32_t nfv = (xf >= 0 && xf < nx) ? plane_b : 0u;
-            pg1[j % kAheadX] = buf_ld(buf(g1p, nin), off);
-            pg2[j % kAheadX] = buf_ld(buf(g2p, nin), off);
-            pfv[j % kAheadX] = buf_ld(buf(fp, nfv), off);
-            g1p += plane;
-            g2p += plane;
-            fp += plane;
+            const int xf = fa + j;
+            const uint32_t og = off + (uint32_t)j * pb;
+            pg1[j % kAheadX] = buf_ld(rg1, og);
+            pg2[j % kAheadX] = buf_ld(rg2, og);
+            pfv[j % kAheadX] = buf_ld(rfv, off + (uint32_t)(xf >= 0 ? xf - fb : BX) * pb);
             s1 += (double)g1 - (double)r1[j];
             s2 += (double)g2 - (double)r2[j];
             r1[j] = g1;
             r2[j] = g2;
-            const int64_t x = p - hix;
+            const int x = xo + j;
             if (x >= 0 && x < nx) {
-                // n = cx * cy * cz, cx the clipped window length along x
-                const double inv_n = inv_yz * kInv[win_len(x, nx, BX)];
+                // n = cx * cy * cz, cx the clipped window length along x; away
+                // from the x faces cx = BX and 1/BX is exact
+                const int cx = win_len32(x, nx, BX);
+                double icx = 1.0 / BX;
+                if (cx != BX) icx = kInv[cx];
+                const double inv_n = inv_yz * icx;
                 const double m1 = s1 * inv_n;
                 double var = s2 * inv_n - m1 * m1;
                 var = var < 0.0 ? 0.0 : var;
                 const float mf = (float)(s + m1);
                 const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
-                if (mean) buf_st(buf(mean + x * plane, plane_b), mf, off);
-                if (stdev) buf_st(buf(stdev + x * plane, plane_b), sf, off);
+                const uint32_t so = off + (uint32_t)(x - xb) * pb;
+                if (mean) buf_st(plane_span(mean, xb, BX, nx, plane_b), mf, so);
+                if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane_b), sf, so);
                 if (mrow) {
                     const bool bit = live && (double)fv > (double)mf + k * (double)sf;
                     const uint64_t word = __ballot(bit);
-                    if ((threadIdx.x & 63) == 0 && live) mrow[x * mstride] = word;
+                    if ((threadIdx.x & 63) == 0 && live) mrow[(int64_t)x * mstride] = word;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -293,13 +475,42 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
 }
 
 template <int BY>
+const char *yz_name(int bz)
+{
+    static const char *const names[4][4] = {
+        {"k_box_yz<8>", "k_box_yz_seg<8,16>", "k_box_yz_seg<8,32>", "k_box_yz_seg<8,64>"},
+        {"k_box_yz<16>", "k_box_yz_seg<16,16>", "k_box_yz_seg<16,32>", "k_box_yz_seg<16,64>"},
+        {"k_box_yz<32>", "k_box_yz_seg<32,16>", "k_box_yz_seg<32,32>", "k_box_yz_seg<32,64>"},
+        {"k_box_yz<64>", "k_box_yz_seg<64,16>", "k_box_yz_seg<64,32>", "k_box_yz_seg<64,64>"}};
+    const int r = BY == 8 ? 0 : BY == 16 ? 1 : BY == 32 ? 2 : 3;
+    const int c = bz == 16 ? 1 : bz == 32 ? 2 : bz == 64 ? 3 : 0;
+    return names[r][c];
+}
+
+template <int BY>
 hipError_t box_yz(const float *F, Dims d, int bz, const double *shift, float *G1, float *G2,
                   hipStream_t s)
 {
     const int64_t jobs = d.nx * ((d.nz + 63) / 64);
-    prof::Scope scope(BY == 64 ? "k_box_yz<64>" : BY == 32 ? "k_box_yz<32>" : BY == 16 ? "k_box_yz<16>" : "k_box_yz<8>", s);
-    hipLaunchKernelGGL(k_box_yz<BY>, dim3((unsigned)((jobs + 3) / 4)), dim3(kThreads), 0, s, F,
-                       d.nx, d.ny, d.nz, bz, shift, G1, G2);
+    const dim3 grid((unsigned)((jobs + 3) / 4));
+    prof::Scope scope(yz_name<BY>(bz), s);
+    switch (bz) {
+    case 16:
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 16>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+                           d.nz, shift, G1, G2);
+        break;
+    case 32:
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 32>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+                           d.nz, shift, G1, G2);
+        break;
+    case 64:
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 64>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+                           d.nz, shift, G1, G2);
+        break;
+    default:
+        hipLaunchKernelGGL(k_box_yz<BY>, grid, dim3(kThreads), 0, s, F, d.nx, d.ny, d.nz, bz,
+                           shift, G1, G2);
+    }
     return hipGetLastError();
 }
 
@@ -346,7 +557,9 @@ XFn x_fn(int bx)
 
 bool stats_fast_path(Box b, Dims d)
 {
-    return yz_fn(b.by) && x_fn(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d);
+    // the x walk addresses BX + 1 planes with 32-bit offsets
+    const bool x_fits = (int64_t)(b.bx + 1) * d.ny * d.nz * 4 < ((int64_t)1 << 31);
+    return yz_fn(b.by) && x_fn(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d) && x_fits;
 }
 
 hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,

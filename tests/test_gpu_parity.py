@@ -81,6 +81,9 @@ STATS_CASES = [
     ((9, 5, 70), (16, 16, 16), 0.0),   # box longer than x and y
     ((16, 16, 96), (5, 7, 9), 250.0),  # odd boxes, large offset (shift matters)
     ((1, 1, 300), (1, 1, 64), 0.0),
+    ((30, 40, 300), (64, 64, 64), 1000.0),   # large offset through the segmented z window
+    ((6, 70, 100), (8, 32, 32), 0.0),
+    ((7, 33, 47), (8, 16, 16), 0.0),          # nz below one strip
 ]
 
 
