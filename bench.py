@@ -6,7 +6,9 @@ six-filter bank (sigma_xy in {1,2,4} x sigma_z in {2,8}, truncated at 3 sigma),
 64^3 local-statistics boxes and the mean + 4 std selection: every filter is
 applied, its local mean/std computed and its mask written.  The cube is in
 HBM before the timed region starts; only the masks are produced (the
-measured configuration; F, mean and std stay in workspace).
+measured configuration; F, mean and std stay in workspace).  The same step
+is then timed with the cube, spectral intermediate and F stored as FP16 and
+as BF16 (reported under "storage16"; the headline value is FP32).
 
 Prints one JSON line: GVoxel-filters/s over the timed steps, the dominant
 kernel's roofline (algorithmic bytes per launch over its live hipEvent
@@ -140,6 +142,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-storage16", action="store_true",
+                    help="skip the FP16/BF16-storage timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +212,32 @@ def main() -> int:
                     "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
                     "algorithmic_bytes_per_launch": alg, "share_of_step": round(ms / total_ms, 3)}
 
+    # the same step with the cube, T1 and F stored in 16 bits (window sums FP32)
+    storage16 = {}
+    if not args.no_storage16:
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            c16 = cube.to(dt)
+            p16 = B.FindPlan([c16], w.filters, w.box, w.k)
+            for _ in range(args.warmup):
+                p16.run()
+            B.profile_reset()
+            B.profile_enable(True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                p16.run()
+            e1.record()
+            torch.cuda.synchronize()
+            B.profile_enable(False)
+            t16 = e0.elapsed_time(e1) / args.steps
+            k16 = B.profile_collect()
+            storage16[name] = {
+                "value": round(V * len(w.filters) / (t16 * 1e-3) / 1e9, 3),
+                "ms_per_step": round(t16, 4),
+                "kernels": {k: {"launches": n, "avg_ms": ms / n} for k, (n, ms) in k16.items()}}
+            print(f"# {name} storage: {t16:.3f} ms/step", file=sys.stderr, flush=True)
+            del p16, c16
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, d, args.cpu_seconds)
@@ -232,6 +262,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "storage16": storage16 or None,
     }
     print(json.dumps(line), flush=True)
     return 0

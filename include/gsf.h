@@ -64,8 +64,8 @@ typedef enum gsf_status {
 
 typedef enum gsf_dtype {
     GSF_F32 = 0,              /* IEEE binary32 */
-    GSF_F16 = 1,              /* IEEE binary16 (storage only; not accepted yet) */
-    GSF_BF16 = 2              /* bfloat16 (storage only; not accepted yet) */
+    GSF_F16 = 1,              /* IEEE binary16, storage only */
+    GSF_BF16 = 2              /* bfloat16, storage only */
 } gsf_dtype;
 
 typedef struct gsf_dims {
@@ -84,7 +84,7 @@ typedef struct gsf_box {
 
 typedef struct gsf_cube {
     const void *data;         /* device pointer to the cube */
-    gsf_dtype dtype;          /* storage type of data */
+    gsf_dtype dtype;          /* storage type of data (F32, F16 or BF16) */
     gsf_dims dims;            /* dims of the array at `data` */
     int32_t halo[3];          /* input-only border per side; must be 0 in this build */
 } gsf_cube;
@@ -96,10 +96,13 @@ typedef struct gsf_cube {
 gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *bytes);
 
 /* out = Eq. 2 applied to `in` with filter *f (zero outside the cube).
- * in, out: nx*ny*nz elements of in_t / out_t (both GSF_F32 in this build);
- * they must not overlap.  ws: at least gsf_filter3d_workspace_size bytes
- * (may be NULL when that figure is 0).  FP32 arithmetic, taps summed in the
- * fixed order -r..r per axis. */
+ * in, out: nx*ny*nz elements of in_t / out_t, which must be the same type
+ * (GSF_F32, GSF_F16 or GSF_BF16; otherwise GSF_ERR_UNSUPPORTED); they must
+ * not overlap.  ws: at least gsf_filter3d_workspace_size bytes (may be NULL
+ * when that figure is 0).  FP32 arithmetic, taps summed in the fixed order
+ * -r..r per axis; with 16-bit storage the spectral-pass intermediate is
+ * stored in that type too, and every stored value is rounded to nearest
+ * even. */
 gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_filter *f,
                         void *out, gsf_dtype out_t, void *ws, size_t ws_bytes, void *stream);
 
@@ -110,9 +113,10 @@ gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes);
 
 /* mean[v] = (1/n) sum_W F,  stdev[v] = sqrt(max(0, (1/n) sum_W (F-s)^2 - ((1/n) sum_W (F-s))^2))
  * over the clipped window W(v) of box b, s a shift computed on the device
- * from F.  F: nx*ny*nz elements of t (GSF_F32).  mean, stdev: nx*ny*nz
- * floats; either may be NULL if not wanted (not both).  Outputs must not
- * overlap F or each other. */
+ * from F.  F: nx*ny*nz elements of t (GSF_F32, GSF_F16 or GSF_BF16; 16-bit
+ * values are widened exactly).  mean, stdev: nx*ny*nz floats in every case;
+ * either may be NULL if not wanted (not both).  The window sums are FP32 or
+ * wider whatever t is.  Outputs must not overlap F or each other. */
 gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b,
                            float *mean, float *stdev, void *ws, size_t ws_bytes, void *stream);
 
@@ -120,7 +124,8 @@ gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b,
 
 /* mask bit of v = F[v] > thr[v], thr = (double)mean[v] + k * (double)stdev[v]
  * evaluated in FP64 with each operation rounded once (no fused multiply-add),
- * comparison strict, F promoted exactly.  mask: nx*ny*ceil(nz/64) words
+ * comparison strict, F (of type t: GSF_F32, GSF_F16 or GSF_BF16) promoted
+ * exactly; mean and stdev are floats.  mask: nx*ny*ceil(nz/64) words
  * (layout above).  Given identical inputs the result is bit-exact. */
 gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const float *stdev,
                          gsf_dims d, double k, uint64_t *mask, void *stream);
@@ -136,8 +141,11 @@ gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const 
  * above (the mask equals gsf_threshold of the F, mean and std produced here).
  * masks[c*nfilt + j]: mask of cube c, filter j (required).
  * F_out, mean_out, std_out: NULL, or arrays of ncubes*nfilt device pointers
- * (each may be NULL) receiving the filtered cube (F32), local mean and local
- * std.  ws: at least gsf_find_workspace_size bytes. */
+ * (each may be NULL) receiving the filtered cube (in the cube's dtype), local
+ * mean and local std (floats).  A cube may be stored as GSF_F32, GSF_F16 or
+ * GSF_BF16; its spectral-pass intermediate and F are then stored in that
+ * type, the window sums stay FP32.  ws: at least gsf_find_workspace_size
+ * bytes (sized for FP32, enough for every storage type). */
 gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
                     gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
                     float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,

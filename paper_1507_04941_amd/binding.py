@@ -1,8 +1,10 @@
 """ctypes binding of libgsf (include/gsf.h) for torch tensors on a ROCm device.
 
 Argument marshalling only: every step of the path runs in the library's HIP
-kernels.  Tensors must be contiguous, on the current HIP device, and of the
-dtype the call expects; torch supplies device memory and the stream
+kernels.  Tensors must be contiguous and on the current HIP device.  Cubes
+and filtered cubes are float32, float16 or bfloat16 (the storage type is
+taken from the tensor); local mean and std are float32.  torch supplies
+device memory and the stream
 (``torch.cuda.current_stream().cuda_stream``).  When ``libgsf.so`` is missing
 this module raises; there is no fallback.
 """
@@ -124,16 +126,24 @@ def _stream(device=None) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _cube(t: torch.Tensor, name: str) -> torch.Tensor:
+_DTYPES = {torch.float32: GSF_F32, torch.float16: GSF_F16, torch.bfloat16: GSF_BF16}
+
+
+def _cube(t: torch.Tensor, name: str, storage: bool = False) -> torch.Tensor:
+    """Check a 3-D device tensor; `storage` cubes may also be float16/bfloat16."""
     if not isinstance(t, torch.Tensor) or t.dim() != 3:
         raise ValueError(f"{name} must be a 3-D tensor (nx, ny, nz)")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on a ROCm device")
-    if t.dtype != torch.float32:
-        raise ValueError(f"{name} must be float32")
+    if t.dtype not in (_DTYPES if storage else (torch.float32,)):
+        raise ValueError(f"{name} must be " + ("float32, float16 or bfloat16" if storage else "float32"))
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
+
+
+def gsf_dtype(t: torch.Tensor) -> int:
+    return _DTYPES[t.dtype]
 
 
 def mask_words(shape) -> int:
@@ -167,17 +177,18 @@ def filter3d_workspace_size(shape, f) -> int:
 
 def filter3d(cube: torch.Tensor, f, out: torch.Tensor | None = None,
              ws: torch.Tensor | None = None) -> torch.Tensor:
-    """Eq. 2: the cube filtered by one (sigma_xy, sigma_z[, truncate]) Gaussian."""
-    cube = _cube(cube, "cube")
+    """Eq. 2: the cube filtered by one (sigma_xy, sigma_z[, truncate]) Gaussian,
+    stored in the cube's dtype."""
+    cube = _cube(cube, "cube", storage=True)
     if out is None:
         out = torch.empty_like(cube)
-    _cube(out, "out")
+    _cube(out, "out", storage=True)
     need = filter3d_workspace_size(cube.shape, f)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cube.device)
-    _check(lib().gsf_filter3d(cube.data_ptr(), GSF_F32, _dims(cube.shape), ctypes.byref(_filter(f)),
-                              out.data_ptr(), GSF_F32, ws.data_ptr(), ws.numel(),
-                              _stream(cube.device)))
+    _check(lib().gsf_filter3d(cube.data_ptr(), gsf_dtype(cube), _dims(cube.shape),
+                              ctypes.byref(_filter(f)), out.data_ptr(), gsf_dtype(out),
+                              ws.data_ptr(), ws.numel(), _stream(cube.device)))
     return out
 
 
@@ -189,14 +200,15 @@ def local_stats_workspace_size(shape, box) -> int:
 
 def local_stats(F: torch.Tensor, box, want_mean: bool = True, want_std: bool = True,
                 ws: torch.Tensor | None = None):
-    """§3.3: per-voxel local mean and std of F over the clipped box window."""
-    F = _cube(F, "F")
-    mean = torch.empty_like(F) if want_mean else None
-    std = torch.empty_like(F) if want_std else None
+    """§3.3: per-voxel local mean and std of F over the clipped box window
+    (float32 outputs for any storage type of F)."""
+    F = _cube(F, "F", storage=True)
+    mean = torch.empty(F.shape, dtype=torch.float32, device=F.device) if want_mean else None
+    std = torch.empty(F.shape, dtype=torch.float32, device=F.device) if want_std else None
     need = local_stats_workspace_size(F.shape, box)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=F.device)
-    _check(lib().gsf_local_stats(F.data_ptr(), GSF_F32, _dims(F.shape), _box(box),
+    _check(lib().gsf_local_stats(F.data_ptr(), gsf_dtype(F), _dims(F.shape), _box(box),
                                  mean.data_ptr() if mean is not None else None,
                                  std.data_ptr() if std is not None else None,
                                  ws.data_ptr(), ws.numel(), _stream(F.device)))
@@ -206,10 +218,10 @@ def local_stats(F: torch.Tensor, box, want_mean: bool = True, want_std: bool = T
 def threshold(F: torch.Tensor, mean: torch.Tensor, std: torch.Tensor, k: float,
               mask: torch.Tensor | None = None) -> torch.Tensor:
     """Selection F > mean + k*std, packed along z into int64 words (nx, ny, W)."""
-    F, mean, std = _cube(F, "F"), _cube(mean, "mean"), _cube(std, "std")
+    F, mean, std = _cube(F, "F", storage=True), _cube(mean, "mean"), _cube(std, "std")
     if mask is None:
         mask = empty_mask(F.shape, F.device)
-    _check(lib().gsf_threshold(F.data_ptr(), GSF_F32, mean.data_ptr(), std.data_ptr(),
+    _check(lib().gsf_threshold(F.data_ptr(), gsf_dtype(F), mean.data_ptr(), std.data_ptr(),
                                _dims(F.shape), float(k), mask.data_ptr(), _stream(F.device)))
     return mask
 
@@ -217,9 +229,9 @@ def threshold(F: torch.Tensor, mean: torch.Tensor, std: torch.Tensor, k: float,
 def _cube_structs(cubes):
     arr = (Cube * len(cubes))()
     for i, c in enumerate(cubes):
-        c = _cube(c, f"cubes[{i}]")
+        c = _cube(c, f"cubes[{i}]", storage=True)
         arr[i].data = c.data_ptr()
-        arr[i].dtype = GSF_F32
+        arr[i].dtype = gsf_dtype(c)
         arr[i].dims = _dims(c.shape)
         arr[i].halo[0] = arr[i].halo[1] = arr[i].halo[2] = 0
     return arr
@@ -240,14 +252,17 @@ class FindPlan:
 
     def __init__(self, cubes, filters, box, k: float, want_F: bool = False,
                  want_stats: bool = False):
-        self.cubes = [_cube(c, f"cubes[{i}]") for i, c in enumerate(cubes)]
+        self.cubes = [_cube(c, f"cubes[{i}]", storage=True) for i, c in enumerate(cubes)]
         self.filters = [tuple(f) for f in filters]
         dev = self.cubes[0].device
         nc, nf = len(self.cubes), len(self.filters)
         self.masks = [[empty_mask(c.shape, dev) for _ in range(nf)] for c in self.cubes]
+        f32 = dict(dtype=torch.float32, device=dev)
         self.F = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_F else None
-        self.mean = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_stats else None
-        self.std = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_stats else None
+        self.mean = ([[torch.empty(c.shape, **f32) for _ in range(nf)] for c in self.cubes]
+                     if want_stats else None)
+        self.std = ([[torch.empty(c.shape, **f32) for _ in range(nf)] for c in self.cubes]
+                    if want_stats else None)
         self._carr = _cube_structs(self.cubes)
         self._farr = (Filter * nf)(*[_filter(f) for f in self.filters])
         self._box = _box(box)

@@ -93,11 +93,12 @@ gsf_status check_box(gsf_box b)
 
 gsf_status check_dtype(gsf_dtype t, const char *what)
 {
-    if (t == GSF_F32) return GSF_OK;
-    if (t == GSF_F16 || t == GSF_BF16)
-        return fail(GSF_ERR_UNSUPPORTED, "%s: only GSF_F32 storage is implemented", what);
+    if (t == GSF_F32 || t == GSF_F16 || t == GSF_BF16) return GSF_OK;
     return fail(GSF_ERR_INVALID_ARG, "%s: unknown dtype %d", what, (int)t);
 }
+
+gsf::Store to_store(gsf_dtype t) { return (gsf::Store)(int)t; }
+size_t elem_bytes(gsf_dtype t) { return gsf::store_bytes(to_store(t)); }
 
 gsf_status check_ptr(const void *p, size_t align, const char *what)
 {
@@ -212,7 +213,9 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
         (st = check_ptr(out, 16, "out")) || (st = check_dtype(in_t, "in_t")) ||
         (st = check_dtype(out_t, "out_t")))
         return st;
-    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    if (in_t != out_t)
+        return fail(GSF_ERR_UNSUPPORTED, "in_t and out_t must be the same storage type");
+    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * elem_bytes(in_t);
     const size_t need = filter_ws(d, f);
     if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((st = check_ptr(ws, 16, "ws"))) return st;
@@ -222,10 +225,12 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
     const gsf::Taps tz = make_taps(f->sigma_z, f->truncate);
     const gsf::Dims dd = to_dims(d);
     const hipStream_t s = (hipStream_t)stream;
-    float *T1 = (float *)ws;
-    float *tmp = (float *)((char *)ws + cube_bytes(d));   // generic path only
-    hipError_t e = gsf::launch_zpass((const float *)in, T1, dd, tz, s);
-    if (e == hipSuccess) e = gsf::launch_yx(T1, (float *)out, tmp, dd, txy, nullptr, nullptr, s);
+    // T1 (and the generic path's second scratch cube) are stored in in_t
+    void *T1 = ws;
+    void *tmp = (char *)ws + cube_bytes(d);
+    const gsf::Store sto = to_store(in_t);
+    hipError_t e = gsf::launch_zpass(in, T1, sto, dd, tz, s);
+    if (e == hipSuccess) e = gsf::launch_yx(T1, out, tmp, sto, dd, txy, nullptr, nullptr, s);
     return device_status(e, "gsf_filter3d launch");
 }
 
@@ -249,19 +254,21 @@ gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b, fl
     if (mean && (st = check_ptr(mean, 16, "mean"))) return st;
     if (stdev && (st = check_ptr(stdev, 16, "stdev"))) return st;
     const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t fb = (size_t)(d.nx * d.ny * d.nz) * elem_bytes(t);
     const size_t need = stats_ws(d);
     if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((st = check_ptr(ws, 16, "ws"))) return st;
-    if (overlaps(F, nb, mean, nb) || overlaps(F, nb, stdev, nb) || overlaps(mean, nb, stdev, nb) ||
-        overlaps(ws, need, F, nb) || overlaps(ws, need, mean, nb) || overlaps(ws, need, stdev, nb))
+    if (overlaps(F, fb, mean, nb) || overlaps(F, fb, stdev, nb) || overlaps(mean, nb, stdev, nb) ||
+        overlaps(ws, need, F, fb) || overlaps(ws, need, mean, nb) || overlaps(ws, need, stdev, nb))
         return fail(GSF_ERR_INVALID_ARG, "F, mean, stdev and ws must not overlap");
     const gsf::Dims dd = to_dims(d);
     const StatsWs w = carve_stats((char *)ws, d);
     const hipStream_t s = (hipStream_t)stream;
-    hipError_t e = gsf::launch_mean((const float *)F, dd, w.partials, w.shift, s);
+    const gsf::Store sto = to_store(t);
+    hipError_t e = gsf::launch_mean(F, sto, dd, w.partials, w.shift, s);
     if (e == hipSuccess)
-        e = gsf::launch_stats((const float *)F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
-                              mean, stdev, nullptr, 0.0, s);
+        e = gsf::launch_stats(F, sto, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4, mean, stdev,
+                              nullptr, 0.0, s);
     return device_status(e, "gsf_local_stats launch");
 }
 
@@ -275,10 +282,11 @@ gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const fl
         return st;
     if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
     const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t fb = (size_t)(d.nx * d.ny * d.nz) * elem_bytes(t);
     const size_t mb = (size_t)to_dims(d).words() * sizeof(uint64_t);
-    if (overlaps(mask, mb, F, nb) || overlaps(mask, mb, mean, nb) || overlaps(mask, mb, stdev, nb))
+    if (overlaps(mask, mb, F, fb) || overlaps(mask, mb, mean, nb) || overlaps(mask, mb, stdev, nb))
         return fail(GSF_ERR_INVALID_ARG, "mask must not overlap its inputs");
-    return device_status(gsf::launch_threshold((const float *)F, mean, stdev, to_dims(d), k, mask,
+    return device_status(gsf::launch_threshold(F, to_store(t), mean, stdev, to_dims(d), k, mask,
                                                (hipStream_t)stream),
                          "gsf_threshold launch");
 }
@@ -342,21 +350,23 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
         if ((st = check_ptr(q.data, 16, "cube data"))) return st;
-        const size_t nb = (size_t)(q.dims.nx * q.dims.ny * q.dims.nz) * sizeof(float);
+        const size_t nv = (size_t)(q.dims.nx * q.dims.ny * q.dims.nz);
+        const size_t nb = nv * sizeof(float);
+        const size_t fb = nv * elem_bytes(q.dtype);   // the cube and F_out
         const size_t mb = (size_t)to_dims(q.dims).words() * sizeof(uint64_t);
-        if (overlaps(ws, need, q.data, nb))
+        if (overlaps(ws, need, q.data, fb))
             return fail(GSF_ERR_INVALID_ARG, "cube %d overlaps the workspace", c);
         for (int32_t j = 0; j < nfilt; ++j) {
             const int64_t o = (int64_t)c * nfilt + j;
             if ((st = check_ptr(masks[o], 8, "masks[i]"))) return st;
             const void *outs[4] = {masks[o], F_out ? F_out[o] : nullptr,
                                    mean_out ? mean_out[o] : nullptr, std_out ? std_out[o] : nullptr};
-            const size_t sizes[4] = {mb, nb, nb, nb};
+            const size_t sizes[4] = {mb, fb, nb, nb};
             for (int a = 1; a < 4; ++a)
                 if (outs[a] && (st = check_ptr(outs[a], 16, "F/mean/std output"))) return st;
             for (int a = 0; a < 4; ++a) {
                 if (!outs[a]) continue;
-                if (overlaps(outs[a], sizes[a], q.data, nb) || overlaps(outs[a], sizes[a], ws, need))
+                if (overlaps(outs[a], sizes[a], q.data, fb) || overlaps(outs[a], sizes[a], ws, need))
                     return fail(GSF_ERR_INVALID_ARG, "output of cube %d filter %d overlaps input or ws",
                                 c, j);
                 for (int b2 = a + 1; b2 < 4; ++b2)
@@ -367,8 +377,8 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     }
     const hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
-    float *T1 = (float *)base;
-    float *Fbuf = (float *)(base + cube_bytes(largest));
+    void *T1 = base;                              // in the cube's storage type
+    void *Fbuf = base + cube_bytes(largest);
     const StatsWs w = carve_stats(base + 2 * cube_bytes(largest), largest);
     // The spectral pass depends only on (sigma_z, truncate): run it once per
     // distinct pair and apply every filter that shares it.
@@ -376,27 +386,28 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
         const gsf::Dims dd = to_dims(q.dims);
+        const gsf::Store sto = to_store(q.dtype);
         std::fill(done.begin(), done.end(), 0);
         for (int32_t g = 0; g < nfilt; ++g) {
             if (done[g]) continue;
             const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
-            hipError_t e = gsf::launch_zpass((const float *)q.data, T1, dd, tz, s);
+            hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, tz, s);
             if (e != hipSuccess) return device_status(e, "gsf_find launch");
             for (int32_t j = g; j < nfilt; ++j) {
                 if (done[j] || f[j].sigma_z != f[g].sigma_z || f[j].truncate != f[g].truncate)
                     continue;
                 done[j] = 1;
                 const int64_t o = (int64_t)c * nfilt + j;
-                float *F = (F_out && F_out[o]) ? (float *)F_out[o] : Fbuf;
+                void *F = (F_out && F_out[o]) ? F_out[o] : Fbuf;
                 const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
                 int nparts = 0;
-                e = gsf::launch_yx(T1, F, w.w1, dd, txy, w.partials, &nparts, s);
+                e = gsf::launch_yx(T1, F, w.w1, sto, dd, txy, w.partials, &nparts, s);
                 if (e == hipSuccess)
                     e = nparts > 0 ? gsf::launch_mean_partials(w.partials, nparts, dd.voxels(),
                                                                w.shift, s)
-                                   : gsf::launch_mean(F, dd, w.partials, w.shift, s);
+                                   : gsf::launch_mean(F, sto, dd, w.partials, w.shift, s);
                 if (e == hipSuccess)
-                    e = gsf::launch_stats(F, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
+                    e = gsf::launch_stats(F, sto, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
                                           mean_out ? mean_out[o] : nullptr,
                                           std_out ? std_out[o] : nullptr, masks[o], k, s);
                 if (e != hipSuccess) return device_status(e, "gsf_find launch");

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "gsf_internal.h"
+
 namespace gsf {
 
 // Raw buffer addressing: a descriptor over [base, base + bytes).  A load
@@ -28,5 +32,58 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, float v, uint32
 {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
 }
+
+// ---- storage types ----
+// Cubes are stored as float (FP32), _Float16 (IEEE binary16) or __bf16
+// (bfloat16); kernels compute in FP32, widen on load (exact) and round to
+// nearest even on store.
+template <typename S>
+__device__ __forceinline__ float widen(S v)
+{
+    return (float)v;
+}
+
+template <typename S>
+__device__ __forceinline__ S narrow(float v)
+{
+    return (S)v;
+}
+
+// One element of storage type S through a buffer descriptor; off in bytes.
+template <typename S>
+__device__ __forceinline__ float sbuf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (sizeof(S) == 4) {
+        return buf_ld(r, off);
+    } else {
+        const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+        return (float)__builtin_bit_cast(S, u);
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void sbuf_st(__amdgpu_buffer_rsrc_t r, float v, uint32_t off)
+{
+    if constexpr (sizeof(S) == 4) {
+        buf_st(r, v, off);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (S)v), r,
+                                              (int)off, 0, 0);
+    }
+}
+
+// Host-side dispatch on a storage type: fn receives a null St pointer whose
+// type selects the instantiation.
+template <typename Fn>
+hipError_t with_store(Store st, Fn &&fn)
+{
+    switch (st) {
+    case Store::F16: return fn((_Float16 *)nullptr);
+    case Store::BF16: return fn((__bf16 *)nullptr);
+    default: return fn((float *)nullptr);
+    }
+}
+
+#define GSF_STORE_T(tag) std::remove_pointer_t<decltype(tag)>
 
 }  // namespace gsf

@@ -22,6 +22,10 @@
 // output sums its taps in ascending offset order, as in the definition.
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <string>
+#include <utility>
+
 #include "gsf_device.h"
 #include "gsf_internal.h"
 
@@ -31,19 +35,48 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kZOut = 4 * kThreads;   // z outputs per k_zpass_r block
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ in,
-                                                      float *__restrict__ out, int64_t nz, Taps t)
+// Four consecutive elements (16-byte aligned for FP32, 8-byte for 16-bit).
+template <typename St>
+__device__ __forceinline__ float4 load4(const St *p)
+{
+    if constexpr (sizeof(St) == 4) {
+        return *reinterpret_cast<const float4 *>(p);
+    } else {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        return make_float4(widen(__builtin_bit_cast(St, (unsigned short)(u.x & 0xffffu))),
+                           widen(__builtin_bit_cast(St, (unsigned short)(u.x >> 16))),
+                           widen(__builtin_bit_cast(St, (unsigned short)(u.y & 0xffffu))),
+                           widen(__builtin_bit_cast(St, (unsigned short)(u.y >> 16))));
+    }
+}
+
+template <typename St>
+__device__ __forceinline__ void store4(St *p, const float (&v)[4])
+{
+    if constexpr (sizeof(St) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        const unsigned b0 = __builtin_bit_cast(unsigned short, narrow<St>(v[0]));
+        const unsigned b1 = __builtin_bit_cast(unsigned short, narrow<St>(v[1]));
+        const unsigned b2 = __builtin_bit_cast(unsigned short, narrow<St>(v[2]));
+        const unsigned b3 = __builtin_bit_cast(unsigned short, narrow<St>(v[3]));
+        *reinterpret_cast<uint2 *>(p) = make_uint2(b0 | (b1 << 16), b2 | (b3 << 16));
+    }
+}
+
+template <int R, typename St>
+__global__ __launch_bounds__(kThreads) void k_zpass_r(const St *__restrict__ in,
+                                                      St *__restrict__ out, int64_t nz, Taps t)
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
     __shared__ float4 tile4[kZOut / 4 + NW + 1];
     float *tile = reinterpret_cast<float *>(tile4);
     const int64_t row = blockIdx.x;
     const int64_t z0 = (int64_t)blockIdx.y * kZOut;
-    const float *src = in + row * nz;
+    const St *src = in + row * nz;
     for (int i = threadIdx.x; i < 4 * (kZOut / 4 + NW + 1); i += kThreads) {
         const int64_t z = z0 - R + i;
-        tile[i] = (z >= 0 && z < nz) ? src[z] : 0.0f;
+        tile[i] = (z >= 0 && z < nz) ? widen(src[z]) : 0.0f;
     }
     __syncthreads();
     float w[4 * NW];
@@ -63,25 +96,26 @@ __global__ __launch_bounds__(kThreads) void k_zpass_r(const float *__restrict__ 
         for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
     }
     const int64_t z = z0 + 4 * threadIdx.x;
-    float *dst = out + row * nz + z;
-    if (z + 3 < nz && (((uintptr_t)dst) & 15) == 0) {
-        *reinterpret_cast<float4 *>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    St *dst = out + row * nz + z;
+    if (sizeof(St) == 4 && z + 3 < nz && (((uintptr_t)dst) & 15) == 0) {
+        store4(dst, acc);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (z + k < nz) dst[k] = acc[k];
+            if (z + k < nz) dst[k] = narrow<St>(acc[k]);
     }
 }
 
 // The same spectral pass for rows whose length is a multiple of 4 (so every
-// row starts 16-byte aligned): a block walks kZRows consecutive rows of one
-// 1024-wide z chunk, loading each row with 16-byte loads one row ahead of
-// its use into a double-buffered LDS tile (one barrier per row).
+// row starts aligned for 4-element loads): a block walks kZRows consecutive
+// rows of one 1024-wide z chunk, loading each row with 4-element loads one
+// row ahead of its use into a double-buffered FP32 LDS tile (one barrier per
+// row).
 constexpr int kZRows = 16;
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void k_zpass_rows(const float *__restrict__ in,
-                                                         float *__restrict__ out, int64_t nrows,
+template <int R, typename St>
+__global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
+                                                         St *__restrict__ out, int64_t nrows,
                                                          int64_t nz, Taps t)
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
@@ -100,9 +134,9 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const float *__restrict
     float4 m = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float h = 0.0f;
     {
-        const float *row = in + r0 * nz;
-        if (mine) m = *reinterpret_cast<const float4 *>(row + zm);
-        if (halo) h = row[zh];
+        const St *row = in + r0 * nz;
+        if (mine) m = load4(row + zm);
+        if (halo) h = widen(row[zh]);
     }
     for (int64_t r = r0; r < r1; ++r) {
         const int b = (int)((r - r0) & 1);
@@ -114,9 +148,9 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const float *__restrict
         if (tid < 2 * R) tile[th] = h;
         __syncthreads();
         if (r + 1 < r1) {
-            const float *row = in + (r + 1) * nz;
-            m = mine ? *reinterpret_cast<const float4 *>(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
-            h = halo ? row[zh] : 0.0f;
+            const St *row = in + (r + 1) * nz;
+            m = mine ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
+            h = halo ? widen(row[zh]) : 0.0f;
         }
         float w[4 * NW];
 #pragma unroll
@@ -134,14 +168,13 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const float *__restrict
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
         }
-        if (mine)
-            *reinterpret_cast<float4 *>(out + r * nz + zm) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        if (mine) store4(out + r * nz + zm, acc);
     }
 }
 
-template <int R, int P, int NW>
-__global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
-                                                  float *__restrict__ F, int64_t nx, int64_t ny,
+template <int R, int P, int NW, typename St>
+__global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
+                                                  St *__restrict__ F, int64_t nx, int64_t ny,
                                                   int64_t nz, int64_t xchunk, Taps t,
                                                   double *__restrict__ partials)
 {
@@ -159,18 +192,19 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
     const int64_t xa = (int64_t)blockIdx.z * xchunk;
     const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
     const bool zl = z < nz;
+    constexpr int64_t SZ = sizeof(St);
     const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);
-    const uint32_t row_b = (uint32_t)(nz * 4);
+    const uint32_t plane_b = (uint32_t)(plane * SZ);
+    const uint32_t row_b = (uint32_t)(nz * SZ);
     // rows w, w + NW, ... of the block's TR-row window are this wave's to load;
     // offsets wrap for rows above the cube and read 0 through the range check
     uint32_t ldo[LW];
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
         const int tr = wave + i * NW;
-        ldo[i] = tr < TR ? (uint32_t)(((yb - R + tr) * nz + z) * 4) : kOOB;
+        ldo[i] = tr < TR ? (uint32_t)(((yb - R + tr) * nz + z) * SZ) : kOOB;
     }
-    const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * 4) : kOOB;
+    const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * SZ) : kOOB;
 
     float acc[P][L];
 #pragma unroll
@@ -188,7 +222,7 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
         const bool in = xq >= 0 && xq < nx;
         const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
 #pragma unroll
-        for (int i = 0; i < LW; ++i) r[i] = buf_ld(rt, ldo[i]);
+        for (int i = 0; i < LW; ++i) r[i] = sbuf_ld<St>(rt, ldo[i]);
     };
     auto store_stage = [&](int st, const float (&r)[LW]) {
 #pragma unroll
@@ -237,8 +271,10 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
                 const __amdgpu_buffer_rsrc_t rf = buf(F + xo * plane, plane_b);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    buf_st(rf, acc[q][slot_o], st0 + (uint32_t)q * row_b);
-                    if (zl && y0 + q < ny) fsum += (double)acc[q][slot_o];
+                    // the shift sums the stored (rounded) values
+                    const float v = widen(narrow<St>(acc[q][slot_o]));
+                    sbuf_st<St>(rf, v, st0 + (uint32_t)q * row_b);
+                    if (zl && y0 + q < ny) fsum += (double)v;
                 }
             }
 #pragma unroll
@@ -261,38 +297,43 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
     }
 }
 
-// Timing names per radius (the profile aggregates launches by name).
-const char *const kZNames[] = {
-    "k_zpass_r<0>",  "k_zpass_r<1>",  "k_zpass_r<2>",  "k_zpass_r<3>",  "k_zpass_r<4>",
-    "k_zpass_r<5>",  "k_zpass_r<6>",  "k_zpass_r<7>",  "k_zpass_r<8>",  "k_zpass_r<9>",
-    "k_zpass_r<10>", "k_zpass_r<11>", "k_zpass_r<12>", "k_zpass_r<13>", "k_zpass_r<14>",
-    "k_zpass_r<15>", "k_zpass_r<16>", "k_zpass_r<17>", "k_zpass_r<18>", "k_zpass_r<19>",
-    "k_zpass_r<20>", "k_zpass_r<21>", "k_zpass_r<22>", "k_zpass_r<23>", "k_zpass_r<24>",
-    "k_zpass_r<25>", "k_zpass_r<26>", "k_zpass_r<27>", "k_zpass_r<28>", "k_zpass_r<29>",
-    "k_zpass_r<30>", "k_zpass_r<31>", "k_zpass_r<32>"};
-const char *const kYxNames[] = {
-    "k_yx_r<0>",  "k_yx_r<1>",  "k_yx_r<2>",  "k_yx_r<3>",  "k_yx_r<4>",  "k_yx_r<5>",
-    "k_yx_r<6>",  "k_yx_r<7>",  "k_yx_r<8>",  "k_yx_r<9>",  "k_yx_r<10>", "k_yx_r<11>",
-    "k_yx_r<12>", "k_yx_r<13>", "k_yx_r<14>", "k_yx_r<15>", "k_yx_r<16>"};
-
-template <int R>
-hipError_t zpass_r(const float *in, float *out, Dims d, const Taps &tz, hipStream_t s)
+// Timing names per radius and storage type (the profile aggregates launches
+// by name), built once.
+template <typename St>
+const char *kernel_name(const char *base, int r)
 {
+    static const std::array<std::array<std::string, kMaxFastRz + 1>, 2> tab = [] {
+        std::array<std::array<std::string, kMaxFastRz + 1>, 2> t;
+        const char *bases[2] = {"k_zpass_r", "k_yx_r"};
+        for (int k = 0; k < 2; ++k)
+            for (int i = 0; i <= kMaxFastRz; ++i)
+                t[k][i] = std::string(bases[k]) + "<" + std::to_string(i) + store_suffix<St>() + ">";
+        return t;
+    }();
+    return tab[base[2] == 'z' ? 0 : 1][r].c_str();
+}
+
+template <int R, typename St>
+hipError_t zpass_r(const void *in_, void *out_, Dims d, const Taps &tz, hipStream_t s)
+{
+    const St *in = (const St *)in_;
+    St *out = (St *)out_;
     const int64_t rows = d.nx * d.ny;
     const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
-    prof::Scope scope(kZNames[R], s);
+    prof::Scope scope(kernel_name<St>("k_zpass_r", R), s);
     if (d.nz % 4 == 0) {
         const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
-        hipLaunchKernelGGL(k_zpass_rows<R>, grid, dim3(kThreads), 0, s, in, out, rows, d.nz, tz);
+        hipLaunchKernelGGL((k_zpass_rows<R, St>), grid, dim3(kThreads), 0, s, in, out, rows, d.nz,
+                           tz);
     } else {
-        hipLaunchKernelGGL(k_zpass_r<R>, dim3((unsigned)rows, zt), dim3(kThreads), 0, s, in, out,
-                           d.nz, tz);
+        hipLaunchKernelGGL((k_zpass_r<R, St>), dim3((unsigned)rows, zt), dim3(kThreads), 0, s, in,
+                           out, d.nz, tz);
     }
     return hipGetLastError();
 }
 
-template <int R, int P, int NW>
-hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, double *partials, int *nparts,
+template <int R, int P, int NW, typename St>
+hipError_t yx_r(const void *T, void *F, Dims d, const Taps &txy, double *partials, int *nparts,
                 hipStream_t s)
 {
     const int64_t tz = (d.nz + 63) / 64;
@@ -309,15 +350,36 @@ hipError_t yx_r(const float *T, float *F, Dims d, const Taps &txy, double *parti
     const int64_t blocks = tz * ty * nxc;
     if (!partials || blocks > kMaxPartials) partials = nullptr;
     if (nparts) *nparts = partials ? (int)blocks : 0;
-    prof::Scope scope(kYxNames[R], s);
-    hipLaunchKernelGGL((k_yx_r<R, P, NW>), grid, dim3(64 * NW), 0, s, T, F, d.nx, d.ny, d.nz,
-                       xchunk, txy, partials);
+    prof::Scope scope(kernel_name<St>("k_yx_r", R), s);
+    hipLaunchKernelGGL((k_yx_r<R, P, NW, St>), grid, dim3(64 * NW), 0, s, (const St *)T, (St *)F,
+                       d.nx, d.ny, d.nz, xchunk, txy, partials);
     return hipGetLastError();
 }
 
-using ZFn = hipError_t (*)(const float *, float *, Dims, const Taps &, hipStream_t);
-using YXFn = hipError_t (*)(const float *, float *, Dims, const Taps &, double *, int *,
+using ZFn = hipError_t (*)(const void *, void *, Dims, const Taps &, hipStream_t);
+using YXFn = hipError_t (*)(const void *, void *, Dims, const Taps &, double *, int *,
                             hipStream_t);
+
+template <typename St, int... R>
+const ZFn *ztab_of(std::integer_sequence<int, R...>)
+{
+    static const ZFn tab[] = {nullptr, &zpass_r<R + 1, St>...};
+    return tab;
+}
+
+// 8 waves per block so a block's y tile (8 waves x P rows) is tall enough to
+// amortise the 2R halo rows it re-reads: blocks sweeping x drift apart, so
+// halo rows are not shared through L2 across blocks.  P shrinks as the ring
+// of 2R+1 partial sums per row grows (at most 256 VGPRs per lane).
+template <int R>
+constexpr int yx_rows() { return R <= 6 ? 4 : R <= 12 ? 3 : 1; }
+
+template <typename St, int... R>
+const YXFn *yxtab_of(std::integer_sequence<int, R...>)
+{
+    static const YXFn tab[] = {nullptr, &yx_r<R + 1, yx_rows<R + 1>(), 8, St>...};
+    return tab;
+}
 
 }  // namespace
 
@@ -325,33 +387,28 @@ bool zpass_fast(int rz) { return rz >= 1 && rz <= kMaxFastRz; }
 bool plane_fits(Dims d) { return d.ny * d.nz <= ((int64_t)1 << 28); }
 bool yx_fast(int rxy, Dims d) { return rxy >= 1 && rxy <= kMaxFastRxy && plane_fits(d); }
 
-hipError_t launch_zpass_fast(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s)
+hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Taps &tz,
+                             hipStream_t s)
 {
-    static const ZFn ztab[kMaxFastRz + 1] = {
-        nullptr, &zpass_r<1>, &zpass_r<2>, &zpass_r<3>, &zpass_r<4>, &zpass_r<5>, &zpass_r<6>,
-        &zpass_r<7>, &zpass_r<8>, &zpass_r<9>, &zpass_r<10>, &zpass_r<11>, &zpass_r<12>,
-        &zpass_r<13>, &zpass_r<14>, &zpass_r<15>, &zpass_r<16>, &zpass_r<17>, &zpass_r<18>,
-        &zpass_r<19>, &zpass_r<20>, &zpass_r<21>, &zpass_r<22>, &zpass_r<23>, &zpass_r<24>,
-        &zpass_r<25>, &zpass_r<26>, &zpass_r<27>, &zpass_r<28>, &zpass_r<29>, &zpass_r<30>,
-        &zpass_r<31>, &zpass_r<32>};
     if (!zpass_fast(tz.r)) return hipErrorInvalidValue;
-    return ztab[tz.r](in, T1, d, tz, s);
+    const auto seq = std::make_integer_sequence<int, kMaxFastRz>{};
+    switch (st) {
+    case Store::F16: return ztab_of<_Float16>(seq)[tz.r](in, T1, d, tz, s);
+    case Store::BF16: return ztab_of<__bf16>(seq)[tz.r](in, T1, d, tz, s);
+    default: return ztab_of<float>(seq)[tz.r](in, T1, d, tz, s);
+    }
 }
 
-hipError_t launch_yx_fast(const float *T1, float *F, Dims d, const Taps &txy, double *partials,
-                          int *nparts, hipStream_t s)
+hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Taps &txy,
+                          double *partials, int *nparts, hipStream_t s)
 {
-    // 8 waves per block so a block's y tile (8 waves x P rows) is tall enough
-    // to amortise the 2R halo rows it re-reads: blocks sweeping x drift apart,
-    // so halo rows are not shared through L2 across blocks.  P shrinks as the
-    // ring of 2R+1 partial sums per row grows (at most 256 VGPRs per lane).
-    static const YXFn yxtab[kMaxFastRxy + 1] = {
-        nullptr, &yx_r<1, 4, 8>, &yx_r<2, 4, 8>, &yx_r<3, 4, 8>, &yx_r<4, 4, 8>, &yx_r<5, 4, 8>,
-        &yx_r<6, 4, 8>, &yx_r<7, 3, 8>, &yx_r<8, 3, 8>, &yx_r<9, 3, 8>, &yx_r<10, 3, 8>,
-        &yx_r<11, 3, 8>, &yx_r<12, 3, 8>, &yx_r<13, 1, 8>, &yx_r<14, 1, 8>, &yx_r<15, 1, 8>,
-        &yx_r<16, 1, 8>};
     if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
-    return yxtab[txy.r](T1, F, d, txy, partials, nparts, s);
+    const auto seq = std::make_integer_sequence<int, kMaxFastRxy>{};
+    switch (st) {
+    case Store::F16: return yxtab_of<_Float16>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
+    case Store::BF16: return yxtab_of<__bf16>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
+    default: return yxtab_of<float>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
+    }
 }
 
 }  // namespace gsf

@@ -17,6 +17,18 @@ struct Taps {
     int r;
 };
 
+// Storage type of a cube (values as in gsf_dtype); arithmetic is FP32.
+enum class Store { F32 = 0, F16 = 1, BF16 = 2 };
+
+inline size_t store_bytes(Store s) { return s == Store::F32 ? 4 : 2; }
+
+// Suffix of kernel timing names for a storage type ("" for FP32).
+template <typename St>
+constexpr const char *store_suffix()
+{
+    return sizeof(St) == 4 ? "" : __is_same(St, _Float16) ? ",f16" : ",bf16";
+}
+
 struct Dims {
     int64_t nx, ny, nz;
     int64_t voxels() const { return nx * ny * nz; }
@@ -55,35 +67,39 @@ bool zpass_fast(int rz);
 // Buffer-addressed kernels need one x-plane below 2^30 bytes.
 bool plane_fits(Dims d);
 bool yx_fast(int rxy, Dims d);
-hipError_t launch_zpass_fast(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s);
-hipError_t launch_yx_fast(const float *T1, float *F, Dims d, const Taps &txy, double *partials,
-                          int *nparts, hipStream_t s);
+hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Taps &tz,
+                             hipStream_t s);
+hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Taps &txy,
+                          double *partials, int *nparts, hipStream_t s);
 
 // Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
 // bx in {8, 16, 32, 64}, bz <= 65.  ws G1, G2: two cubes of floats.
 bool stats_fast_path(Box b, Dims d);
-hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,
-                             float *G2, float *mean, float *stdev, uint64_t *mask, double k,
-                             hipStream_t s);
+hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const double *shift,
+                             float *G1, float *G2, float *mean, float *stdev, uint64_t *mask,
+                             double k, hipStream_t s);
 
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
+// Cubes passed as void * hold elements of storage type st.
 // Spectral pass: T1 = gz * in along z.
-hipError_t launch_zpass(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s);
+hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Taps &tz,
+                        hipStream_t s);
 // Spatial passes: F = gxy * (gxy * T1 along y) along x.  tmp is a scratch
 // cube used only by the generic path.  If partials is non-null, per-block
 // FP64 sums of F may be written there; *nparts gets their count (0 if not).
-hipError_t launch_yx(const float *T1, float *F, float *tmp, Dims d, const Taps &txy,
+hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Taps &txy,
                      double *partials, int *nparts, hipStream_t s);
 // shift[0] = mean of F (FP64), full pass over F with a fixed reduction order.
-hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s);
+hipError_t launch_mean(const void *F, Store st, Dims d, double *partials, double *shift,
+                       hipStream_t s);
 // shift[0] = (sum of n partials) / V, fixed order.
 hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double *shift,
                                 hipStream_t s);
 // Local statistics and (optionally) the mask.  ws1..ws4: four scratch cubes.
-hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, float *ws1, float *ws2,
-                        float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
-                        double k, hipStream_t s);
-hipError_t launch_threshold(const float *F, const float *mean, const float *stdev, Dims d,
-                            double k, uint64_t *mask, hipStream_t s);
+hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *shift, float *ws1,
+                        float *ws2, float *ws3, float *ws4, float *mean, float *stdev,
+                        uint64_t *mask, double k, hipStream_t s);
+hipError_t launch_threshold(const void *F, Store st, const float *mean, const float *stdev,
+                            Dims d, double k, uint64_t *mask, hipStream_t s);
 
 }  // namespace gsf

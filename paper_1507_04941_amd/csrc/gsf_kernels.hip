@@ -6,6 +6,7 @@
 // sums of F - s and (F - s)^2.  Selection: F > mean + k*std.
 #include <hip/hip_runtime.h>
 
+#include "gsf_device.h"
 #include "gsf_internal.h"
 
 namespace gsf {
@@ -19,31 +20,33 @@ constexpr int kBlock = 256;   // four wave64s along z
 
 // Spectral (z) pass: a block stages one row segment plus its +-r halo in LDS
 // with coalesced loads, then every lane reads its 2r+1 neighbours from LDS.
-__global__ __launch_bounds__(kBlock) void k_zpass(const float *__restrict__ in,
-                                                  float *__restrict__ out, int64_t nz, Taps t)
+template <typename St>
+__global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
+                                                  St *__restrict__ out, int64_t nz, Taps t)
 {
     extern __shared__ float tile[];
     const int r = t.r;
     const int64_t row = blockIdx.x;
     const int64_t z0 = (int64_t)blockIdx.y * kBlock;
-    const float *src = in + row * nz;
+    const St *src = in + row * nz;
     for (int i = threadIdx.x; i < kBlock + 2 * r; i += kBlock) {
         const int64_t z = z0 - r + i;
-        tile[i] = (z >= 0 && z < nz) ? src[z] : 0.0f;
+        tile[i] = (z >= 0 && z < nz) ? widen(src[z]) : 0.0f;
     }
     __syncthreads();
     const int64_t z = z0 + threadIdx.x;
     if (z < nz) {
         float acc = 0.0f;
         for (int o = 0; o <= 2 * r; ++o) acc = fmaf(t.g[o], tile[threadIdx.x + o], acc);
-        out[row * nz + z] = acc;
+        out[row * nz + z] = narrow<St>(acc);
     }
 }
 
 // Pass along a strided axis (y: stride nz, x: stride ny*nz).  Lanes run
 // along z so every tap load is a coalesced row read.
-__global__ __launch_bounds__(kBlock) void k_strided_pass(const float *__restrict__ in,
-                                                         float *__restrict__ out, int64_t ny,
+template <typename St>
+__global__ __launch_bounds__(kBlock) void k_strided_pass(const St *__restrict__ in,
+                                                         St *__restrict__ out, int64_t ny,
                                                          int64_t nz, int axis_x, int64_t n_axis,
                                                          Taps t)
 {
@@ -54,13 +57,13 @@ __global__ __launch_bounds__(kBlock) void k_strided_pass(const float *__restrict
     const int64_t y = row % ny, x = row / ny;
     const int64_t pos = axis_x ? x : y;
     const int64_t stride = axis_x ? ny * nz : nz;
-    const float *src = in + row * nz + z;
+    const St *src = in + row * nz + z;
     float acc = 0.0f;
     for (int o = -r; o <= r; ++o) {
         const int64_t p = pos + o;
-        if (p >= 0 && p < n_axis) acc = fmaf(t.g[o + r], src[(int64_t)o * stride], acc);
+        if (p >= 0 && p < n_axis) acc = fmaf(t.g[o + r], widen(src[(int64_t)o * stride]), acc);
     }
-    out[row * nz + z] = acc;
+    out[row * nz + z] = narrow<St>(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,7 +81,8 @@ __device__ double block_sum(double v, double *lds)
     return lds[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_partial_sums(const float *__restrict__ F, int64_t V,
+template <typename St>
+__global__ __launch_bounds__(kBlock) void k_partial_sums(const St *__restrict__ F, int64_t V,
                                                          double *__restrict__ partials)
 {
     __shared__ double lds[kBlock];
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_partial_sums(const float *__restrict
     const int64_t a = (int64_t)blockIdx.x * chunk;
     const int64_t b = a + chunk < V ? a + chunk : V;
     double s = 0.0;
-    for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += (double)F[i];
+    for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += (double)widen(F[i]);
     const double tot = block_sum(s, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -115,7 +119,8 @@ __device__ __forceinline__ int64_t win_count(int64_t i, int64_t n, int B)
 }
 
 // z window sums of a = F - s and a^2, one row segment per block staged in LDS.
-__global__ __launch_bounds__(kBlock) void k_zbox(const float *__restrict__ F, int64_t nz, int B,
+template <typename St>
+__global__ __launch_bounds__(kBlock) void k_zbox(const St *__restrict__ F, int64_t nz, int B,
                                                  const double *__restrict__ shift,
                                                  float *__restrict__ Z1, float *__restrict__ Z2)
 {
@@ -126,11 +131,11 @@ __global__ __launch_bounds__(kBlock) void k_zbox(const float *__restrict__ F, in
     const int lo = -(B / 2);
     const int64_t row = blockIdx.x;
     const int64_t z0 = (int64_t)blockIdx.y * kBlock;
-    const float *src = F + row * nz;
+    const St *src = F + row * nz;
     for (int i = threadIdx.x; i < kBlock + B - 1; i += kBlock) {
         const int64_t z = z0 + lo + i;
         double a = 0.0;
-        if (z >= 0 && z < nz) a = (double)src[z] - s;
+        if (z >= 0 && z < nz) a = (double)widen(src[z]) - s;
         a1[i] = (float)a;
         a2[i] = (float)(a * a);
     }
@@ -185,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_ybox(const float *__restrict__ Z1,
 }
 
 // x window sums, then mean/std and the selection bit, packed by wave ballot.
+template <typename St>
 __global__ __launch_bounds__(kBlock) void k_xbox_final(
-    const float *__restrict__ Y1, const float *__restrict__ Y2, const float *__restrict__ F,
+    const float *__restrict__ Y1, const float *__restrict__ Y2, const St *__restrict__ F,
     int64_t nx, int64_t ny, int64_t nz, Box b, const double *__restrict__ shift,
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_xbox_final(
             if (stdev) stdev[i] = sf;
             if (mask) {
                 const double thr = (double)mf + k * (double)sf;
-                bit = (double)F[i] > thr;
+                bit = (double)widen(F[i]) > thr;
             }
         }
         if (mask) {
@@ -237,7 +243,8 @@ __global__ __launch_bounds__(kBlock) void k_xbox_final(
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_threshold(const float *__restrict__ F,
+template <typename St>
+__global__ __launch_bounds__(kBlock) void k_threshold(const St *__restrict__ F,
                                                       const float *__restrict__ mean,
                                                       const float *__restrict__ stdev,
                                                       int64_t nz, double k,
@@ -251,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_threshold(const float *__restrict__ 
     if (z < nz) {
         const int64_t i = row * nz + z;
         const double thr = (double)mean[i] + k * (double)stdev[i];
-        bit = (double)F[i] > thr;
+        bit = (double)widen(F[i]) > thr;
     }
     const uint64_t word = __ballot(bit);
     if ((threadIdx.x & 63) == 0 && z < nz) mask[row * W + z / 64] = word;
@@ -261,35 +268,39 @@ inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_zpass(const float *in, float *T1, Dims d, const Taps &tz, hipStream_t s)
+hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Taps &tz, hipStream_t s)
 {
-    if (zpass_fast(tz.r)) return launch_zpass_fast(in, T1, d, tz, s);
+    if (zpass_fast(tz.r)) return launch_zpass_fast(in, T1, st, d, tz, s);
     const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
-    {
-        prof::Scope scope_("k_zpass", s);
-        hipLaunchKernelGGL(k_zpass, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s, in,
-                           T1, d.nz, tz);
-    }
-    return hipGetLastError();
+    prof::Scope scope_("k_zpass", s);
+    return with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
+        hipLaunchKernelGGL(k_zpass<St>, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s,
+                           (const St *)in, (St *)T1, d.nz, tz);
+        return hipGetLastError();
+    });
 }
 
-hipError_t launch_yx(const float *T1, float *F, float *tmp, Dims d, const Taps &txy,
+hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Taps &txy,
                      double *partials, int *nparts, hipStream_t s)
 {
-    if (yx_fast(txy.r, d)) return launch_yx_fast(T1, F, d, txy, partials, nparts, s);
+    if (yx_fast(txy.r, d)) return launch_yx_fast(T1, F, st, d, txy, partials, nparts, s);
     if (nparts) *nparts = 0;
     const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
-    {
-        prof::Scope scope_("k_strided_pass", s);
-        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, T1, tmp, d.ny, d.nz, 0, d.ny,
-                           txy);
-    }
-    {
-        prof::Scope scope_("k_strided_pass", s);
-        hipLaunchKernelGGL(k_strided_pass, grid, dim3(kBlock), 0, s, (const float *)tmp, F, d.ny,
-                           d.nz, 1, d.nx, txy);
-    }
-    return hipGetLastError();
+    return with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
+        {
+            prof::Scope scope_("k_strided_pass", s);
+            hipLaunchKernelGGL(k_strided_pass<St>, grid, dim3(kBlock), 0, s, (const St *)T1,
+                               (St *)tmp, d.ny, d.nz, 0, d.ny, txy);
+        }
+        {
+            prof::Scope scope_("k_strided_pass", s);
+            hipLaunchKernelGGL(k_strided_pass<St>, grid, dim3(kBlock), 0, s, (const St *)tmp,
+                               (St *)F, d.ny, d.nz, 1, d.nx, txy);
+        }
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double *shift,
@@ -302,56 +313,64 @@ hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double
     return hipGetLastError();
 }
 
-hipError_t launch_mean(const float *F, Dims d, double *partials, double *shift, hipStream_t s)
+hipError_t launch_mean(const void *F, Store st, Dims d, double *partials, double *shift,
+                       hipStream_t s)
 {
-    {
+    const hipError_t e = with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
         prof::Scope scope_("k_partial_sums", s);
-        hipLaunchKernelGGL(k_partial_sums, dim3(kShiftBlocks), dim3(kBlock), 0, s, F, d.voxels(),
-                       partials);
-    }
+        hipLaunchKernelGGL(k_partial_sums<St>, dim3(kShiftBlocks), dim3(kBlock), 0, s,
+                           (const St *)F, d.voxels(), partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     {
         prof::Scope scope_("k_final_mean", s);
         hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, (const double *)partials,
-                       kShiftBlocks, d.voxels(), shift);
+                           kShiftBlocks, d.voxels(), shift);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const float *F, Dims d, Box b, const double *shift, float *ws1, float *ws2,
-                        float *ws3, float *ws4, float *mean, float *stdev, uint64_t *mask,
-                        double k, hipStream_t s)
+hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *shift, float *ws1,
+                        float *ws2, float *ws3, float *ws4, float *mean, float *stdev,
+                        uint64_t *mask, double k, hipStream_t s)
 {
     if (stats_fast_path(b, d))
-        return launch_stats_fast(F, d, b, shift, ws1, ws2, mean, stdev, mask, k, s);
-    const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
-    {
-        prof::Scope scope_("k_zbox", s);
-        hipLaunchKernelGGL(k_zbox, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), zlds, s,
-                       F, d.nz, b.bz, shift, ws1, ws2);
-    }
-    {
-        prof::Scope scope_("k_ybox", s);
-        hipLaunchKernelGGL(k_ybox, dim3((unsigned)d.nx, ztiles(d.nz)), dim3(kBlock), 0, s,
-                       (const float *)ws1, (const float *)ws2, ws3, ws4, d.ny, d.nz, b.by);
-    }
-    {
-        prof::Scope scope_("k_xbox_final", s);
-        hipLaunchKernelGGL(k_xbox_final, dim3((unsigned)d.ny, ztiles(d.nz)), dim3(kBlock), 0, s,
-                       (const float *)ws3, (const float *)ws4, F, d.nx, d.ny, d.nz, b, shift, mean,
-                       stdev, mask, k);
-    }
-    return hipGetLastError();
+        return launch_stats_fast(F, st, d, b, shift, ws1, ws2, mean, stdev, mask, k, s);
+    return with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
+        const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);
+        {
+            prof::Scope scope_("k_zbox", s);
+            hipLaunchKernelGGL(k_zbox<St>, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock),
+                               zlds, s, (const St *)F, d.nz, b.bz, shift, ws1, ws2);
+        }
+        {
+            prof::Scope scope_("k_ybox", s);
+            hipLaunchKernelGGL(k_ybox, dim3((unsigned)d.nx, ztiles(d.nz)), dim3(kBlock), 0, s,
+                               (const float *)ws1, (const float *)ws2, ws3, ws4, d.ny, d.nz, b.by);
+        }
+        {
+            prof::Scope scope_("k_xbox_final", s);
+            hipLaunchKernelGGL(k_xbox_final<St>, dim3((unsigned)d.ny, ztiles(d.nz)), dim3(kBlock), 0,
+                               s, (const float *)ws3, (const float *)ws4, (const St *)F, d.nx, d.ny,
+                               d.nz, b, shift, mean, stdev, mask, k);
+        }
+        return hipGetLastError();
+    });
 }
 
-hipError_t launch_threshold(const float *F, const float *mean, const float *stdev, Dims d,
-                            double k, uint64_t *mask, hipStream_t s)
+hipError_t launch_threshold(const void *F, Store st, const float *mean, const float *stdev,
+                            Dims d, double k, uint64_t *mask, hipStream_t s)
 {
-    {
-        prof::Scope scope_("k_threshold", s);
-        hipLaunchKernelGGL(k_threshold, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), 0,
-                       s, F, mean, stdev, d.nz, k, mask);
-    }
-    return hipGetLastError();
+    prof::Scope scope_("k_threshold", s);
+    return with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
+        hipLaunchKernelGGL(k_threshold<St>, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock),
+                           0, s, (const St *)F, mean, stdev, d.nz, k, mask);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace gsf

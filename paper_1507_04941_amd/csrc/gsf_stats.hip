@@ -18,6 +18,9 @@
 // sums (any window).
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <string>
+
 #include "gsf_device.h"
 #include "gsf_internal.h"
 
@@ -91,8 +94,8 @@ constexpr int kAheadX = 4;   // planes the x walk loads before use
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
-template <int BY>
-__global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F, int64_t nx,
+template <int BY, typename St>
+__global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, int64_t nx,
                                                      int64_t ny, int64_t nz, int bz,
                                                      const double *__restrict__ shift,
                                                      float *__restrict__ G1,
@@ -113,17 +116,20 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
     const int loy = -(BY / 2);
     const int hiy = loy + BY - 1;
     const float s = (float)shift[0];
+    constexpr int64_t SZ = sizeof(St);
     const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);
+    const uint32_t plane_b = (uint32_t)(plane * 4);     // G planes and rows (FP32)
     const uint32_t row_b = (uint32_t)(nz * 4);
+    const uint32_t fplane_b = (uint32_t)(plane * SZ);   // F planes and rows (storage type)
+    const uint32_t frow_b = (uint32_t)(nz * SZ);
     // the two adjacent columns this lane carries: t = 2*lane and 2*lane + 1
     const int64_t zc0 = z0 + loz + 2 * lane;
     const int64_t zc1 = zc0 + 1;
     const bool v0 = (2 * lane < 64 + bz - 1) && zc0 >= 0 && zc0 < nz;
     const bool v1 = (2 * lane + 1 < 64 + bz - 1) && zc1 >= 0 && zc1 < nz;
-    const uint32_t o0 = v0 ? (uint32_t)(zc0 * 4) : kOOB;
-    const uint32_t o1 = v1 ? (uint32_t)(zc1 * 4) : kOOB;
-    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, plane_b);
+    const uint32_t o0 = v0 ? (uint32_t)(zc0 * SZ) : kOOB;
+    const uint32_t o1 = v1 ? (uint32_t)(zc1 * SZ) : kOOB;
+    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, fplane_b);
     const int64_t zo = z0 + lane;
     const uint32_t og = zo < nz ? (uint32_t)(zo * 4) : kOOB;
     const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
@@ -135,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
     float pf0[kAhead], pf1[kAhead];
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) {
-        pf0[j] = buf_ld(rf, o0 + (uint32_t)j * row_b);
-        pf1[j] = buf_ld(rf, o1 + (uint32_t)j * row_b);
+        pf0[j] = sbuf_ld<St>(rf, o0 + (uint32_t)j * frow_b);
+        pf1[j] = sbuf_ld<St>(rf, o1 + (uint32_t)j * frow_b);
     }
     double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of the two columns
     double *q1 = qs[wave][0];
@@ -153,9 +159,9 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const float *__restrict__ F
             const bool row = yin < ny;
             const float e0 = (row && v0) ? pf0[j % kAhead] - s : 0.0f;
             const float e1 = (row && v1) ? pf1[j % kAhead] - s : 0.0f;
-            const uint32_t ra = (uint32_t)(yin + kAhead) * row_b;   // past ny: outside the plane
-            pf0[j % kAhead] = buf_ld(rf, o0 + ra);
-            pf1[j % kAhead] = buf_ld(rf, o1 + ra);
+            const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
+            pf0[j % kAhead] = sbuf_ld<St>(rf, o0 + ra);
+            pf1[j % kAhead] = sbuf_ld<St>(rf, o1 + ra);
             const float l0 = ring0[j], l1 = ring1[j];
             ring0[j] = e0;
             ring1[j] = e1;
@@ -239,8 +245,8 @@ __device__ __forceinline__ void seg_scan4(float (&v)[4])
 // running sums of FP32 increments, rounded once to FP32 before the scans; a
 // scan only adds same-window partial sums, so each window sum is accurate
 // relative to itself.
-template <int BY, int BZ>
-__global__ __launch_bounds__(kThreads) void k_box_yz_seg(const float *__restrict__ F, int64_t nx,
+template <int BY, int BZ, typename St>
+__global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ F, int64_t nx,
                                                          int64_t ny64, int64_t nz64,
                                                          const double *__restrict__ shift,
                                                          float *__restrict__ G1,
@@ -260,17 +266,19 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const float *__restrict
     const int z0 = (int)(job % nstrips) * 64;
     const int hiy = -(BY / 2) + BY - 1;
     const float s = (float)shift[0];
+    constexpr uint32_t SZ = sizeof(St);
     const int64_t plane = (int64_t)ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);
+    const uint32_t plane_b = (uint32_t)(plane * 4);     // G planes and rows (FP32)
     const uint32_t row_b = (uint32_t)nz * 4u;
+    const uint32_t frow_b = (uint32_t)nz * SZ;          // F rows (storage type)
     const int seg = lane / BZ, q = lane % BZ;
     const int za = z0 - BZ / 2 + seg * BZ + (BZ - 1 - q);
     const int zb = z0 - BZ / 2 + (seg + 1) * BZ + q;
     const bool va = za >= 0 && za < nz;
     const bool vb = zb >= 0 && zb < nz;
-    const uint32_t oa = va ? (uint32_t)za * 4u : kOOB;
-    const uint32_t ob = vb ? (uint32_t)zb * 4u : kOOB;
-    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, plane_b);
+    const uint32_t oa = va ? (uint32_t)za * SZ : kOOB;
+    const uint32_t ob = vb ? (uint32_t)zb * SZ : kOOB;
+    const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, (uint32_t)(plane * SZ));
     // output column of this lane and the lane holding the head it adds
     const int zo = z0 + seg * BZ + (BZ - 1 - q);
     const uint32_t og = zo < nz ? (uint32_t)zo * 4u : kOOB;
@@ -284,8 +292,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const float *__restrict
     float pfa[kAhead], pfb[kAhead];
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) {
-        pfa[j] = buf_ld(rf, oa + (uint32_t)j * row_b);
-        pfb[j] = buf_ld(rf, ob + (uint32_t)j * row_b);
+        pfa[j] = sbuf_ld<St>(rf, oa + (uint32_t)j * frow_b);
+        pfb[j] = sbuf_ld<St>(rf, ob + (uint32_t)j * frow_b);
     }
     double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of columns A and B
     const int nsteps = ny + hiy;
@@ -297,9 +305,9 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const float *__restrict
             const bool row = yin < ny;
             const float ea = (row && va) ? pfa[j % kAhead] - s : 0.0f;
             const float eb = (row && vb) ? pfb[j % kAhead] - s : 0.0f;
-            const uint32_t ra = (uint32_t)(yin + kAhead) * row_b;   // past ny: outside the plane
-            pfa[j % kAhead] = buf_ld(rf, oa + ra);
-            pfb[j % kAhead] = buf_ld(rf, ob + ra);
+            const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
+            pfa[j % kAhead] = sbuf_ld<St>(rf, oa + ra);
+            pfb[j % kAhead] = sbuf_ld<St>(rf, ob + ra);
             const float la = ringa[j], lb = ringb[j];
             ringa[j] = ea;
             ringb[j] = eb;
@@ -359,12 +367,13 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v)
 // plane inside it with (plane - p) * plane bytes added to the lane's 32-bit
 // offset (the range-checked one); a plane past the clip lies outside the
 // range and reads 0 / drops the store.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const float *c, int p, int span,
-                                                             int nx, uint32_t plane_b)
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const E *c, int p, int span, int nx,
+                                                             uint32_t plane)
 {
     const int n = p < nx ? (nx - p < span ? nx - p : span) : 0;
     const int pc = p < nx ? p : nx;
-    return buf(c + (int64_t)pc * (plane_b / 4), (uint32_t)n * plane_b);
+    return buf(c + (int64_t)pc * plane, (uint32_t)n * plane * (uint32_t)sizeof(E));
 }
 
 // One lane per (y, z), 256 consecutive z per block; walks x.  Per step the
@@ -374,9 +383,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const float *c, int
 // 32-bit: every BX steps the kernel sets up descriptors over the next BX
 // planes of each stream and steps through them with scalar offsets, which
 // needs BX + 1 planes to span less than 2^31 bytes.
-template <int BX>
+template <int BX, typename St>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
-    const float *__restrict__ G1, const float *__restrict__ G2, const float *__restrict__ F,
+    const float *__restrict__ G1, const float *__restrict__ G2, const St *__restrict__ F,
     int64_t nx64, int64_t ny64, int64_t nz64, int by, int bz, const double *__restrict__ shift,
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
@@ -387,9 +396,13 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int z = blockIdx.x * kThreads + threadIdx.x;
     const bool live = z < nz;
-    const uint32_t plane_b = (uint32_t)ny * (uint32_t)nz * 4u;
+    constexpr uint32_t SZ = sizeof(St);
+    const uint32_t plane = (uint32_t)ny * (uint32_t)nz;
+    const uint32_t plane_b = plane * 4u;                 // G, mean, std (FP32)
+    const uint32_t fplane_b = plane * SZ;                // F (storage type)
     // offset of (y, z) inside a plane; dead lanes address outside every range
     const uint32_t off = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * 4u : kOOB;
+    const uint32_t offf = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * SZ : kOOB;
     const int W = (nz + 63) / 64;
     const int hix = -(BX / 2) + BX - 1;
     const double s = (double)(float)shift[0];   // the same FP32 shift the sums used
@@ -405,15 +418,15 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     // pa - hix of F (output)
     float pg1[kAheadX], pg2[kAheadX], pfv[kAheadX];
     {
-        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, kAheadX, nx, plane_b);
-        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, kAheadX, nx, plane_b);
-        const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, kAheadX, nx, plane_b);
+        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, kAheadX, nx, plane);
+        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, kAheadX, nx, plane);
+        const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, kAheadX, nx, plane);
 #pragma unroll
         for (int j = 0; j < kAheadX; ++j) {
             const int xf = j - hix;
             pg1[j] = buf_ld(q1, off + (uint32_t)j * plane_b);
             pg2[j] = buf_ld(q2, off + (uint32_t)j * plane_b);
-            pfv[j] = buf_ld(qf, off + (uint32_t)(xf >= 0 ? xf : BX) * plane_b);
+            pfv[j] = sbuf_ld<St>(qf, offf + (uint32_t)(xf >= 0 ? xf : BX) * fplane_b);
         }
     }
     double s1 = 0.0, s2 = 0.0;
@@ -431,9 +444,10 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
         const int xo = p0 - hix;
         const int xb = xo > 0 ? xo : 0;
         const uint32_t pb = opaque(plane_b);
-        const __amdgpu_buffer_rsrc_t rg1 = plane_span(G1, ga, BX, nx, plane_b);
-        const __amdgpu_buffer_rsrc_t rg2 = plane_span(G2, ga, BX, nx, plane_b);
-        const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane_b);
+        const uint32_t pbf = opaque(fplane_b);
+        const __amdgpu_buffer_rsrc_t rg1 = plane_span(G1, ga, BX, nx, plane);
+        const __amdgpu_buffer_rsrc_t rg2 = plane_span(G2, ga, BX, nx, plane);
+        const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane);
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
             const float g1 = pg1[j % kAheadX], g2 = pg2[j % kAheadX];
@@ -442,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
             const uint32_t og = off + (uint32_t)j * pb;
             pg1[j % kAheadX] = buf_ld(rg1, og);
             pg2[j % kAheadX] = buf_ld(rg2, og);
-            pfv[j % kAheadX] = buf_ld(rfv, off + (uint32_t)(xf >= 0 ? xf - fb : BX) * pb);
+            pfv[j % kAheadX] = sbuf_ld<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
             s1 += (double)g1 - (double)r1[j];
             s2 += (double)g2 - (double)r2[j];
             r1[j] = g1;
@@ -461,8 +475,8 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
                 const float mf = (float)(s + m1);
                 const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
                 const uint32_t so = off + (uint32_t)(x - xb) * pb;
-                if (mean) buf_st(plane_span(mean, xb, BX, nx, plane_b), mf, so);
-                if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane_b), sf, so);
+                if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
+                if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
                 if (mrow) {
                     const bool bit = live && (double)fv > (double)mf + k * (double)sf;
                     const uint64_t word = __ballot(bit);
@@ -474,81 +488,103 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     }
 }
 
-template <int BY>
-const char *yz_name(int bz)
+// Timing names by window lengths and storage type, built once.
+template <typename St>
+const char *yz_name(int by, int bz)
 {
-    static const char *const names[4][4] = {
-        {"k_box_yz<8>", "k_box_yz_seg<8,16>", "k_box_yz_seg<8,32>", "k_box_yz_seg<8,64>"},
-        {"k_box_yz<16>", "k_box_yz_seg<16,16>", "k_box_yz_seg<16,32>", "k_box_yz_seg<16,64>"},
-        {"k_box_yz<32>", "k_box_yz_seg<32,16>", "k_box_yz_seg<32,32>", "k_box_yz_seg<32,64>"},
-        {"k_box_yz<64>", "k_box_yz_seg<64,16>", "k_box_yz_seg<64,32>", "k_box_yz_seg<64,64>"}};
-    const int r = BY == 8 ? 0 : BY == 16 ? 1 : BY == 32 ? 2 : 3;
+    static const std::array<std::array<std::string, 4>, 4> tab = [] {
+        std::array<std::array<std::string, 4>, 4> t;
+        const int bys[4] = {8, 16, 32, 64}, bzs[4] = {0, 16, 32, 64};
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c)
+                t[r][c] = c == 0 ? "k_box_yz<" + std::to_string(bys[r]) + store_suffix<St>() + ">"
+                                 : "k_box_yz_seg<" + std::to_string(bys[r]) + "," +
+                                       std::to_string(bzs[c]) + store_suffix<St>() + ">";
+        return t;
+    }();
+    const int r = by == 8 ? 0 : by == 16 ? 1 : by == 32 ? 2 : 3;
     const int c = bz == 16 ? 1 : bz == 32 ? 2 : bz == 64 ? 3 : 0;
-    return names[r][c];
+    return tab[r][c].c_str();
 }
 
-template <int BY>
-hipError_t box_yz(const float *F, Dims d, int bz, const double *shift, float *G1, float *G2,
+template <typename St>
+const char *x_name(int bx)
+{
+    static const std::array<std::string, 4> tab = [] {
+        std::array<std::string, 4> t;
+        const int bxs[4] = {8, 16, 32, 64};
+        for (int i = 0; i < 4; ++i)
+            t[i] = "k_box_x_select<" + std::to_string(bxs[i]) + store_suffix<St>() + ">";
+        return t;
+    }();
+    return tab[bx == 8 ? 0 : bx == 16 ? 1 : bx == 32 ? 2 : 3].c_str();
+}
+
+template <int BY, typename St>
+hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G1, float *G2,
                   hipStream_t s)
 {
+    const St *F = (const St *)F_;
     const int64_t jobs = d.nx * ((d.nz + 63) / 64);
     const dim3 grid((unsigned)((jobs + 3) / 4));
-    prof::Scope scope(yz_name<BY>(bz), s);
+    prof::Scope scope(yz_name<St>(BY, bz), s);
     switch (bz) {
     case 16:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 16>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 16, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
                            d.nz, shift, G1, G2);
         break;
     case 32:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 32>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 32, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
                            d.nz, shift, G1, G2);
         break;
     case 64:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 64>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 64, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
                            d.nz, shift, G1, G2);
         break;
     default:
-        hipLaunchKernelGGL(k_box_yz<BY>, grid, dim3(kThreads), 0, s, F, d.nx, d.ny, d.nz, bz,
+        hipLaunchKernelGGL((k_box_yz<BY, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny, d.nz, bz,
                            shift, G1, G2);
     }
     return hipGetLastError();
 }
 
-template <int BX>
-hipError_t box_x_select(const float *G1, const float *G2, const float *F, Dims d, Box b,
+template <int BX, typename St>
+hipError_t box_x_select(const float *G1, const float *G2, const void *F, Dims d, Box b,
                         const double *shift, float *mean, float *stdev, uint64_t *mask, double k,
                         hipStream_t s)
 {
     const dim3 grid((unsigned)((d.nz + kThreads - 1) / kThreads), (unsigned)d.ny);
-    prof::Scope scope(BX == 64 ? "k_box_x_select<64>" : BX == 32 ? "k_box_x_select<32>" : BX == 16 ? "k_box_x_select<16>" : "k_box_x_select<8>", s);
-    hipLaunchKernelGGL(k_box_x_select<BX>, grid, dim3(kThreads), 0, s, G1, G2, F, d.nx, d.ny, d.nz,
-                       b.by, b.bz, shift, mean, stdev, mask, k);
+    prof::Scope scope(x_name<St>(BX), s);
+    hipLaunchKernelGGL((k_box_x_select<BX, St>), grid, dim3(kThreads), 0, s, G1, G2, (const St *)F,
+                       d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
     return hipGetLastError();
 }
 
-using YZFn = hipError_t (*)(const float *, Dims, int, const double *, float *, float *,
+using YZFn = hipError_t (*)(const void *, Dims, int, const double *, float *, float *,
                             hipStream_t);
-using XFn = hipError_t (*)(const float *, const float *, const float *, Dims, Box, const double *,
+using XFn = hipError_t (*)(const float *, const float *, const void *, Dims, Box, const double *,
                            float *, float *, uint64_t *, double, hipStream_t);
 
+template <typename St>
 YZFn yz_fn(int by)
 {
     switch (by) {
-    case 8: return &box_yz<8>;
-    case 16: return &box_yz<16>;
-    case 32: return &box_yz<32>;
-    case 64: return &box_yz<64>;
+    case 8: return &box_yz<8, St>;
+    case 16: return &box_yz<16, St>;
+    case 32: return &box_yz<32, St>;
+    case 64: return &box_yz<64, St>;
     default: return nullptr;
     }
 }
 
+template <typename St>
 XFn x_fn(int bx)
 {
     switch (bx) {
-    case 8: return &box_x_select<8>;
-    case 16: return &box_x_select<16>;
-    case 32: return &box_x_select<32>;
-    case 64: return &box_x_select<64>;
+    case 8: return &box_x_select<8, St>;
+    case 16: return &box_x_select<16, St>;
+    case 32: return &box_x_select<32, St>;
+    case 64: return &box_x_select<64, St>;
     default: return nullptr;
     }
 }
@@ -559,17 +595,21 @@ bool stats_fast_path(Box b, Dims d)
 {
     // the x walk addresses BX + 1 planes with 32-bit offsets
     const bool x_fits = (int64_t)(b.bx + 1) * d.ny * d.nz * 4 < ((int64_t)1 << 31);
-    return yz_fn(b.by) && x_fn(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d) && x_fits;
+    return yz_fn<float>(b.by) && x_fn<float>(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d) &&
+           x_fits;
 }
 
-hipError_t launch_stats_fast(const float *F, Dims d, Box b, const double *shift, float *G1,
-                             float *G2, float *mean, float *stdev, uint64_t *mask, double k,
-                             hipStream_t s)
+hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const double *shift,
+                             float *G1, float *G2, float *mean, float *stdev, uint64_t *mask,
+                             double k, hipStream_t s)
 {
     if (!stats_fast_path(b, d)) return hipErrorInvalidValue;
-    hipError_t e = yz_fn(b.by)(F, d, b.bz, shift, G1, G2, s);
-    if (e != hipSuccess) return e;
-    return x_fn(b.bx)(G1, G2, F, d, b, shift, mean, stdev, mask, k, s);
+    return with_store(st, [&](auto *tag) {
+        using St = GSF_STORE_T(tag);
+        hipError_t e = yz_fn<St>(b.by)(F, d, b.bz, shift, G1, G2, s);
+        if (e != hipSuccess) return e;
+        return x_fn<St>(b.bx)(G1, G2, F, d, b, shift, mean, stdev, mask, k, s);
+    });
 }
 
 }  // namespace gsf

@@ -101,7 +101,7 @@ def test_calls_reject_bad_pointers_before_launch(L):
     assert L.gsf_filter3d(4096, 0, d, ctypes.byref(f), 65536, 0, 1 << 20, 16, None) == 3
     # in/out overlap
     assert L.gsf_filter3d(4096, 0, d, ctypes.byref(f), 4096 + 256, 0, 1 << 24, 1 << 20, None) == 1
-    # unsupported storage type
+    # mixed storage types (F16 in, F32 out)
     assert L.gsf_filter3d(4096, 1, d, ctypes.byref(f), 65536, 0, 1 << 20, 1 << 20, None) == 2
     # unknown dtype
     assert L.gsf_filter3d(4096, 7, d, ctypes.byref(f), 65536, 0, 1 << 20, 1 << 20, None) == 1
@@ -134,8 +134,8 @@ def test_find_validation(L):
     cubes[0].halo[2] = -1
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
     cubes[0].halo[2] = 0
-    cubes[0].dtype = 2
-    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 2
+    cubes[0].dtype = 9   # unknown storage type
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
     cubes[0].dtype = 0
     masks2 = (ctypes.c_void_p * 1)(4096 + 64)  # mask overlaps the cube
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks2, None, None, None, ws, need, None) == 1

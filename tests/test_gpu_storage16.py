@@ -1,0 +1,124 @@
+"""16-bit storage: cubes stored as binary16 or bfloat16, with the spectral
+intermediate and F stored in that type, FP32 arithmetic and FP32 window sums.
+
+Kernel-only parity: the oracle runs on the input rounded to the 16-bit type
+(what the library actually reads), so the remaining error is the library's own
+rounding of T1 and F; bounds are REL16 (statistics) and REL16_F (filtered
+values) times the usual scales.  The
+end-to-end error against the oracle on the original FP32 cube is logged."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1507_04941_amd import binding as B
+from paper_1507_04941_amd import synth
+from tests.parity import (REL16, REL16_F, check_filtered, check_mask, check_stats, cube_scale,
+                          log, round16, sigma_f)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TORCH = {"f16": torch.float16, "bf16": torch.bfloat16}
+
+
+def _gpu16(a: np.ndarray, name: str) -> torch.Tensor:
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(TORCH[name])
+    return t.to(DEV)
+
+
+def _f32(t: torch.Tensor) -> np.ndarray:
+    return t.float().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.SMALL
+    return w, synth.workload_cube(w)
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16"])
+@pytest.mark.parametrize("shape,f", [((64, 64, 128), (2.0, 4.0)), ((33, 17, 300), (1.0, 8.0)),
+                                     ((40, 9, 65), (1.5, 2.5)), ((5, 7, 9), (2.0, 4.0))])
+def test_filter3d_16(name, shape, f):
+    log(f"filter3d {name} shape={shape} filter={f}")
+    d = synth.make_noise(shape, seed=sum(shape)) + 0.5
+    d16 = round16(d, name)
+    Fg = B.filter3d(_gpu16(d16, name), f)
+    assert Fg.dtype == TORCH[name]
+    Fo = oracle.filter3d(d16, *f)
+    worst = check_filtered(_f32(Fg), Fo, f, cube_scale(d16), rel=REL16_F[name])
+    e2e = np.abs(_f32(Fg) - oracle.filter3d(d, *f)).max() / (sigma_f(f) * cube_scale(d))
+    log(f"  kernel-only worst/bound={worst:.3g}  end-to-end max|err|/sigma_F={e2e:.3g}")
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16"])
+@pytest.mark.parametrize("shape,box", [((40, 80, 130), (32, 64, 16)), ((16, 16, 96), (5, 7, 9)),
+                                       ((5, 3, 70), (64, 64, 64))])
+def test_local_stats_16(name, shape, box):
+    log(f"local_stats {name} shape={shape} box={box}")
+    d = synth.make_cube(shape, n_sources=2, seed=7)
+    f = (1.0, 2.0)
+    F16 = round16(oracle.filter3d(d, *f), name)
+    mg, sg = B.local_stats(_gpu16(F16, name), box)
+    mo, so = oracle.local_stats(F16.astype(np.float64), box)
+    # F is the same 16-bit array on both sides: the FP32 bound applies
+    wm, ws = check_stats(mg.cpu().numpy(), sg.cpu().numpy(), mo, so, sigma_f(f) * cube_scale(d))
+    log(f"  worst mean/bound={wm:.3g} std/bound={ws:.3g}")
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16"])
+def test_threshold_16_bit_exact(name):
+    log(f"threshold {name}")
+    rng = np.random.default_rng(5)
+    shape = (9, 7, 130)
+    F = round16(rng.standard_normal(shape), name)
+    m = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    s = np.abs(rng.standard_normal(shape) * 0.3).astype(np.float32)
+    t = rng.random(shape) < 0.1                  # exact ties: F == mean + 4 std
+    m[t] = 1.0
+    s[t] = 0.25
+    F[t] = 2.0
+    words = B.threshold(_gpu16(F, name), torch.from_numpy(m).to(DEV), torch.from_numpy(s).to(DEV), 4.0)
+    np.testing.assert_array_equal(B.unpack_mask(words, shape),
+                                  oracle.threshold_f32(F, m, s, 4.0).astype(bool))
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16"])
+def test_find_16_small_workload(small, name):
+    w, d = small
+    d16 = round16(d, name)
+    log(f"find {name} {w.name}")
+    out = B.find(_gpu16(d16, name), w.filters, w.box, w.k, want_F=True, want_stats=True)
+    ref = oracle.find(d16, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    e2e = oracle.find(d, w.filters, w.box, w.k, want_F=True, want_stats=True)
+    scale = cube_scale(d16)
+    rel = REL16[name]
+    for j, f in enumerate(w.filters):
+        Fg = _f32(out["F"][0][j])
+        mg = out["mean"][0][j].cpu().numpy()
+        sg = out["std"][0][j].cpu().numpy()
+        wf = check_filtered(Fg, ref["F"][j], f, scale, what=f"F[{j}]", rel=REL16_F[name])
+        wm, ws = check_stats(mg, sg, ref["mean"][j], ref["std"][j], sigma_f(f) * scale,
+                             what=f"stats[{j}]", rel=rel)
+        mask_g = B.unpack_mask(out["mask"][0][j], d.shape)
+        band = check_mask(mask_g, ref["F"][j], ref["mean"][j], ref["std"][j], w.k, f, scale,
+                          what=f"mask[{j}]", rel=rel, rel_f=REL16_F[name])
+        # end to end against the FP32 cube, in units of the 1e-3 bar
+        floor = sigma_f(f) * cube_scale(d)
+        es = np.max(np.abs(sg - e2e["std"][j]) / np.maximum(e2e["std"][j], floor)) / 1e-3
+        ef = np.max(np.abs(Fg - e2e["F"][j]) / np.maximum(np.abs(e2e["F"][j]), floor)) / 1e-3
+        diff = int((mask_g != e2e["mask"][j].astype(bool)).sum())
+        log(f"  filter {f}: kernel-only F/bound={wf:.3g} mean/bound={wm:.3g} std/bound={ws:.3g} "
+            f"band={band}; end-to-end F/1e-3={ef:.3g} std/1e-3={es:.3g} mask diffs={diff}")
+        again = B.threshold(out["F"][0][j], out["mean"][0][j], out["std"][0][j], w.k)
+        assert torch.equal(again, out["mask"][0][j])
+
+
+def test_mixed_storage_types_rejected():
+    log("filter3d mixed storage types")
+    d = torch.zeros((4, 4, 8), dtype=torch.float16, device=DEV)
+    out = torch.empty((4, 4, 8), dtype=torch.float32, device=DEV)
+    with pytest.raises(B.GsfError) as e:
+        B.filter3d(d, (1.0, 1.0), out=out)
+    assert e.value.status == B.GSF_ERR_UNSUPPORTED
