@@ -61,6 +61,30 @@ __device__ __forceinline__ float sbuf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
     }
 }
 
+// Raw form of a loaded element: the float itself for FP32, the 16 bits for
+// 16-bit types.  Prefetched values stay raw until the step that uses them, so
+// the widening does not wait on the load in the step that issues it.
+template <typename S>
+using raw_t = std::conditional_t<sizeof(S) == 4, float, unsigned short>;
+
+template <typename S>
+__device__ __forceinline__ raw_t<S> sbuf_ld_raw(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (sizeof(S) == 4)
+        return buf_ld(r, off);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+
+template <typename S>
+__device__ __forceinline__ float from_raw(raw_t<S> v)
+{
+    if constexpr (sizeof(S) == 4)
+        return v;
+    else
+        return (float)__builtin_bit_cast(S, v);
+}
+
 template <typename S>
 __device__ __forceinline__ void sbuf_st(__amdgpu_buffer_rsrc_t r, float v, uint32_t off)
 {

@@ -218,23 +218,24 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     int64_t base = p_start >= 0 ? (p_start / L) * L : -(((-p_start) + L - 1) / L) * L;
 
     // a plane outside [0, nx) gets an empty range, so its rows read 0
-    auto load_plane = [&](int64_t xq, float (&r)[LW]) {
+    // loads stay raw until stored to LDS two planes later
+    auto load_plane = [&](int64_t xq, raw_t<St> (&r)[LW]) {
         const bool in = xq >= 0 && xq < nx;
         const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
 #pragma unroll
-        for (int i = 0; i < LW; ++i) r[i] = sbuf_ld<St>(rt, ldo[i]);
+        for (int i = 0; i < LW; ++i) r[i] = sbuf_ld_raw<St>(rt, ldo[i]);
     };
-    auto store_stage = [&](int st, const float (&r)[LW]) {
+    auto store_stage = [&](int st, const raw_t<St> (&r)[LW]) {
 #pragma unroll
         for (int i = 0; i < LW; ++i) {
             const int tr = wave + i * NW;
-            if (tr < TR) stage[st][tr][lane] = r[i];
+            if (tr < TR) stage[st][tr][lane] = from_raw<St>(r[i]);
         }
     };
     // prologue: plane base in LDS, planes base+1 and base+2 in registers.
     // Each step writes plane xp+1 to its stage and issues the loads of plane
     // xp+3, so a load has two planes of compute to arrive.
-    float ra[LW], rb[LW];
+    raw_t<St> ra[LW], rb[LW];
     load_plane(base, ra);
     store_stage(base % S < 0 ? base % S + S : base % S, ra);
     load_plane(base + 1, ra);

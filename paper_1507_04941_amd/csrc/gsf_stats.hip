@@ -138,11 +138,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
 #pragma unroll
     for (int j = 0; j < BY; ++j) ring0[j] = ring1[j] = 0.0f;
     // rows kAhead steps ahead; rows past the cube and dead columns load 0
-    float pf0[kAhead], pf1[kAhead];
+    raw_t<St> pf0[kAhead], pf1[kAhead];
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) {
-        pf0[j] = sbuf_ld<St>(rf, o0 + (uint32_t)j * frow_b);
-        pf1[j] = sbuf_ld<St>(rf, o1 + (uint32_t)j * frow_b);
+        pf0[j] = sbuf_ld_raw<St>(rf, o0 + (uint32_t)j * frow_b);
+        pf1[j] = sbuf_ld_raw<St>(rf, o1 + (uint32_t)j * frow_b);
     }
     double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of the two columns
     double *q1 = qs[wave][0];
@@ -157,11 +157,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
         for (int j = 0; j < BY; ++j) {
             const int64_t yin = y0 + j;                   // yin mod BY == j
             const bool row = yin < ny;
-            const float e0 = (row && v0) ? pf0[j % kAhead] - s : 0.0f;
-            const float e1 = (row && v1) ? pf1[j % kAhead] - s : 0.0f;
+            const float e0 = (row && v0) ? from_raw<St>(pf0[j % kAhead]) - s : 0.0f;
+            const float e1 = (row && v1) ? from_raw<St>(pf1[j % kAhead]) - s : 0.0f;
             const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
-            pf0[j % kAhead] = sbuf_ld<St>(rf, o0 + ra);
-            pf1[j % kAhead] = sbuf_ld<St>(rf, o1 + ra);
+            pf0[j % kAhead] = sbuf_ld_raw<St>(rf, o0 + ra);
+            pf1[j % kAhead] = sbuf_ld_raw<St>(rf, o1 + ra);
             const float l0 = ring0[j], l1 = ring1[j];
             ring0[j] = e0;
             ring1[j] = e1;
@@ -289,11 +289,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ 
     float ringa[BY], ringb[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ringa[j] = ringb[j] = 0.0f;
-    float pfa[kAhead], pfb[kAhead];
+    raw_t<St> pfa[kAhead], pfb[kAhead];
 #pragma unroll
     for (int j = 0; j < kAhead; ++j) {
-        pfa[j] = sbuf_ld<St>(rf, oa + (uint32_t)j * frow_b);
-        pfb[j] = sbuf_ld<St>(rf, ob + (uint32_t)j * frow_b);
+        pfa[j] = sbuf_ld_raw<St>(rf, oa + (uint32_t)j * frow_b);
+        pfb[j] = sbuf_ld_raw<St>(rf, ob + (uint32_t)j * frow_b);
     }
     double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of columns A and B
     const int nsteps = ny + hiy;
@@ -303,11 +303,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ 
         for (int j = 0; j < BY; ++j) {
             const int yin = y0 + j;                       // yin mod BY == j
             const bool row = yin < ny;
-            const float ea = (row && va) ? pfa[j % kAhead] - s : 0.0f;
-            const float eb = (row && vb) ? pfb[j % kAhead] - s : 0.0f;
+            const float ea = (row && va) ? from_raw<St>(pfa[j % kAhead]) - s : 0.0f;
+            const float eb = (row && vb) ? from_raw<St>(pfb[j % kAhead]) - s : 0.0f;
             const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
-            pfa[j % kAhead] = sbuf_ld<St>(rf, oa + ra);
-            pfb[j % kAhead] = sbuf_ld<St>(rf, ob + ra);
+            pfa[j % kAhead] = sbuf_ld_raw<St>(rf, oa + ra);
+            pfb[j % kAhead] = sbuf_ld_raw<St>(rf, ob + ra);
             const float la = ringa[j], lb = ringb[j];
             ringa[j] = ea;
             ringb[j] = eb;
@@ -416,7 +416,8 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
     // loads issued kAheadX steps early: plane pa of G (entering) and plane
     // pa - hix of F (output)
-    float pg1[kAheadX], pg2[kAheadX], pfv[kAheadX];
+    float pg1[kAheadX], pg2[kAheadX];
+    raw_t<St> pfv[kAheadX];
     {
         const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, kAheadX, nx, plane);
         const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, kAheadX, nx, plane);
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
             const int xf = j - hix;
             pg1[j] = buf_ld(q1, off + (uint32_t)j * plane_b);
             pg2[j] = buf_ld(q2, off + (uint32_t)j * plane_b);
-            pfv[j] = sbuf_ld<St>(qf, offf + (uint32_t)(xf >= 0 ? xf : BX) * fplane_b);
+            pfv[j] = sbuf_ld_raw<St>(qf, offf + (uint32_t)(xf >= 0 ? xf : BX) * fplane_b);
         }
     }
     double s1 = 0.0, s2 = 0.0;
@@ -451,12 +452,12 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
             const float g1 = pg1[j % kAheadX], g2 = pg2[j % kAheadX];
-            const float fv = pfv[j % kAheadX];
+            const raw_t<St> fraw = pfv[j % kAheadX];
             const int xf = fa + j;
             const uint32_t og = off + (uint32_t)j * pb;
             pg1[j % kAheadX] = buf_ld(rg1, og);
             pg2[j % kAheadX] = buf_ld(rg2, og);
-            pfv[j % kAheadX] = sbuf_ld<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
+            pfv[j % kAheadX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
             s1 += (double)g1 - (double)r1[j];
             s2 += (double)g2 - (double)r2[j];
             r1[j] = g1;
@@ -478,6 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
                 if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
                 if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
                 if (mrow) {
+                    const float fv = from_raw<St>(fraw);
                     const bool bit = live && (double)fv > (double)mf + k * (double)sf;
                     const uint64_t word = __ballot(bit);
                     if ((threadIdx.x & 63) == 0 && live) mrow[(int64_t)x * mstride] = word;
