@@ -86,8 +86,15 @@ typedef struct gsf_cube {
     const void *data;         /* device pointer to the cube */
     gsf_dtype dtype;          /* storage type of data (F32, F16 or BF16) */
     gsf_dims dims;            /* dims of the array at `data` */
-    int32_t halo[3];          /* input-only border per side; must be 0 in this build */
+    int32_t halo[3];          /* input-only border per side along x, y, z (>= 0) */
 } gsf_cube;
+/* A cube with a halo is a core of dims - 2*halo voxels surrounded by halo[a]
+ * voxels of input on each side of axis a (how a large cube is cut into
+ * independently processed sub-cubes, §3.1).  The filter reads the whole array
+ * at `data` (zero outside it); F, the local statistics and the mask are
+ * produced for the core only, with statistics windows clipped to the core, so
+ * every output array of the cube has the core's dims.  halo = 0 is the plain
+ * case. */
 
 /* ---- Filtering: Eq. 2 (§2.1), c_u[x][y][z] = sum_o d[x+o_x][y+o_y][z+o_z] f[o] ---- */
 

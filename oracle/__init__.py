@@ -242,3 +242,28 @@ def find(d, filters, box, k: float, want_F: bool = False, want_stats: bool = Fal
         out["mean"] = mu
         out["std"] = sd
     return out
+
+
+def find_halo(d, halo, filters, box, k: float):
+    """The whole path for a cube with an input-only border (the halo, per
+    side along x, y, z): Eq. 2 over the whole array (zero outside it), the
+    filtered core cut out, then local mean/std (§3.3) and the selection on
+    that core as if it were the whole cube.  A plain composition of
+    filter3d, local_stats and threshold.
+
+    Returns dict with 'F', 'mean', 'std' (nfilt, core) float64 and 'mask'
+    (nfilt, core) uint8."""
+    d = _f32(d)
+    hx, hy, hz = (int(h) for h in halo)
+    core = (slice(hx, d.shape[0] - hx), slice(hy, d.shape[1] - hy), slice(hz, d.shape[2] - hz))
+    out = {"F": [], "mean": [], "std": [], "mask": []}
+    for f in filters:
+        t = float(f[2]) if len(f) > 2 else 3.0
+        F = np.ascontiguousarray(filter3d(d, float(f[0]), float(f[1]), t)[core])
+        mu, sd = local_stats(F, box)
+        out["F"].append(F)
+        out["mean"].append(mu)
+        out["std"].append(sd)
+        out["mask"].append(threshold(F, mu, sd, k))
+    return {key: np.stack(v) for key, v in out.items()}
+

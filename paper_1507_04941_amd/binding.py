@@ -226,19 +226,35 @@ def threshold(F: torch.Tensor, mean: torch.Tensor, std: torch.Tensor, k: float,
     return mask
 
 
-def _cube_structs(cubes):
+def _halos(halos, n):
+    """None, one (hx, hy, hz) for every cube, or one per cube."""
+    if halos is None:
+        return [(0, 0, 0)] * n
+    if len(halos) == 3 and all(isinstance(v, (int, np.integer)) for v in halos):
+        return [tuple(int(v) for v in halos)] * n
+    if len(halos) != n:
+        raise ValueError("halos: one (hx, hy, hz) per cube")
+    return [tuple(int(v) for v in h) for h in halos]
+
+
+def core_shape(shape, halo) -> tuple:
+    return tuple(int(s) - 2 * int(h) for s, h in zip(shape, halo))
+
+
+def _cube_structs(cubes, halos=None):
+    hs = _halos(halos, len(cubes))
     arr = (Cube * len(cubes))()
     for i, c in enumerate(cubes):
         c = _cube(c, f"cubes[{i}]", storage=True)
         arr[i].data = c.data_ptr()
         arr[i].dtype = gsf_dtype(c)
         arr[i].dims = _dims(c.shape)
-        arr[i].halo[0] = arr[i].halo[1] = arr[i].halo[2] = 0
+        arr[i].halo[0], arr[i].halo[1], arr[i].halo[2] = hs[i]
     return arr
 
 
-def find_workspace_size(cubes, filters, box) -> int:
-    carr = _cube_structs(cubes)
+def find_workspace_size(cubes, filters, box, halos=None) -> int:
+    carr = _cube_structs(cubes, halos)
     farr = (Filter * len(filters))(*[_filter(f) for f in filters])
     n = _SZ(0)
     _check(lib().gsf_find_workspace_size(carr, len(cubes), farr, len(filters), _box(box),
@@ -251,19 +267,22 @@ class FindPlan:
     timed loop only re-issues the C call."""
 
     def __init__(self, cubes, filters, box, k: float, want_F: bool = False,
-                 want_stats: bool = False):
+                 want_stats: bool = False, halos=None):
         self.cubes = [_cube(c, f"cubes[{i}]", storage=True) for i, c in enumerate(cubes)]
         self.filters = [tuple(f) for f in filters]
+        self.halos = _halos(halos, len(self.cubes))
+        self.cores = [core_shape(c.shape, h) for c, h in zip(self.cubes, self.halos)]
         dev = self.cubes[0].device
         nc, nf = len(self.cubes), len(self.filters)
-        self.masks = [[empty_mask(c.shape, dev) for _ in range(nf)] for c in self.cubes]
+        self.masks = [[empty_mask(s, dev) for _ in range(nf)] for s in self.cores]
         f32 = dict(dtype=torch.float32, device=dev)
-        self.F = [[torch.empty_like(c) for _ in range(nf)] for c in self.cubes] if want_F else None
-        self.mean = ([[torch.empty(c.shape, **f32) for _ in range(nf)] for c in self.cubes]
+        self.F = ([[torch.empty(s, dtype=c.dtype, device=dev) for _ in range(nf)]
+                   for c, s in zip(self.cubes, self.cores)] if want_F else None)
+        self.mean = ([[torch.empty(s, **f32) for _ in range(nf)] for s in self.cores]
                      if want_stats else None)
-        self.std = ([[torch.empty(c.shape, **f32) for _ in range(nf)] for c in self.cubes]
+        self.std = ([[torch.empty(s, **f32) for _ in range(nf)] for s in self.cores]
                     if want_stats else None)
-        self._carr = _cube_structs(self.cubes)
+        self._carr = _cube_structs(self.cubes, self.halos)
         self._farr = (Filter * nf)(*[_filter(f) for f in self.filters])
         self._box = _box(box)
         self.k = float(k)
@@ -277,7 +296,7 @@ class FindPlan:
         self._F = ptrs(self.F)
         self._mu = ptrs(self.mean)
         self._sd = ptrs(self.std)
-        need = find_workspace_size(self.cubes, self.filters, box)
+        need = find_workspace_size(self.cubes, self.filters, box, self.halos)
         self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
         self.device = dev
 
@@ -313,14 +332,16 @@ def profile_collect() -> dict:
     return out
 
 
-def find(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False) -> dict:
+def find(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False,
+         halos=None) -> dict:
     """The whole path over a batch of cubes: for each cube and filter, Eq. 2,
-    local mean/std (§3.3) and the mask F > mean + k*std.
+    local mean/std (§3.3) and the mask F > mean + k*std.  With halos, each
+    cube's outputs cover its core (see gsf_cube in gsf.h).
 
     Returns {'mask': [[words]], 'F': [[...]] | None, 'mean': ..., 'std': ...}
     indexed [cube][filter]."""
     if isinstance(cubes, torch.Tensor):
         cubes = [cubes]
-    plan = FindPlan(cubes, filters, box, k, want_F=want_F, want_stats=want_stats)
+    plan = FindPlan(cubes, filters, box, k, want_F=want_F, want_stats=want_stats, halos=halos)
     plan.run()
     return {"mask": plan.masks, "F": plan.F, "mean": plan.mean, "std": plan.std}

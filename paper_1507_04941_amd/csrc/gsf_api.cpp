@@ -229,8 +229,9 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
     void *T1 = ws;
     void *tmp = (char *)ws + cube_bytes(d);
     const gsf::Store sto = to_store(in_t);
-    hipError_t e = gsf::launch_zpass(in, T1, sto, dd, tz, s);
-    if (e == hipSuccess) e = gsf::launch_yx(T1, out, tmp, sto, dd, txy, nullptr, nullptr, s);
+    const gsf::Halo h = gsf::no_halo(dd);
+    hipError_t e = gsf::launch_zpass(in, T1, sto, dd, h, tz, s);
+    if (e == hipSuccess) e = gsf::launch_yx(T1, out, tmp, sto, dd, h, txy, nullptr, nullptr, s);
     return device_status(e, "gsf_filter3d launch");
 }
 
@@ -293,6 +294,13 @@ gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const fl
 
 namespace {
 
+// The core of a cube: its dims less the halo on both sides of each axis.
+gsf_dims core_dims(const gsf_cube &q)
+{
+    return gsf_dims{q.dims.nx - 2 * (int64_t)q.halo[0], q.dims.ny - 2 * (int64_t)q.halo[1],
+                    q.dims.nz - 2 * (int64_t)q.halo[2]};
+}
+
 gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
                        gsf_box b, gsf_dims *largest)
 {
@@ -309,8 +317,9 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
         if ((st = check_dtype(q.dtype, "cube dtype"))) return st;
         if (q.halo[0] < 0 || q.halo[1] < 0 || q.halo[2] < 0)
             return fail(GSF_ERR_INVALID_ARG, "cube %d: negative halo", c);
-        if (q.halo[0] || q.halo[1] || q.halo[2])
-            return fail(GSF_ERR_UNSUPPORTED, "cube %d: halos are not implemented", c);
+        const gsf_dims core = core_dims(q);
+        if (core.nx < 1 || core.ny < 1 || core.nz < 1)
+            return fail(GSF_ERR_INVALID_ARG, "cube %d: halo leaves no core", c);
         const int64_t v = q.dims.nx * q.dims.ny * q.dims.nz;
         if (v > best) { best = v; *largest = q.dims; }
     }
@@ -350,11 +359,13 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
         if ((st = check_ptr(q.data, 16, "cube data"))) return st;
-        const size_t nv = (size_t)(q.dims.nx * q.dims.ny * q.dims.nz);
+        const gsf_dims core = core_dims(q);
+        const size_t qb = (size_t)(q.dims.nx * q.dims.ny * q.dims.nz) * elem_bytes(q.dtype);
+        const size_t nv = (size_t)(core.nx * core.ny * core.nz);   // outputs cover the core
         const size_t nb = nv * sizeof(float);
-        const size_t fb = nv * elem_bytes(q.dtype);   // the cube and F_out
-        const size_t mb = (size_t)to_dims(q.dims).words() * sizeof(uint64_t);
-        if (overlaps(ws, need, q.data, fb))
+        const size_t fb = nv * elem_bytes(q.dtype);   // F_out
+        const size_t mb = (size_t)to_dims(core).words() * sizeof(uint64_t);
+        if (overlaps(ws, need, q.data, qb))
             return fail(GSF_ERR_INVALID_ARG, "cube %d overlaps the workspace", c);
         for (int32_t j = 0; j < nfilt; ++j) {
             const int64_t o = (int64_t)c * nfilt + j;
@@ -366,7 +377,7 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                 if (outs[a] && (st = check_ptr(outs[a], 16, "F/mean/std output"))) return st;
             for (int a = 0; a < 4; ++a) {
                 if (!outs[a]) continue;
-                if (overlaps(outs[a], sizes[a], q.data, fb) || overlaps(outs[a], sizes[a], ws, need))
+                if (overlaps(outs[a], sizes[a], q.data, qb) || overlaps(outs[a], sizes[a], ws, need))
                     return fail(GSF_ERR_INVALID_ARG, "output of cube %d filter %d overlaps input or ws",
                                 c, j);
                 for (int b2 = a + 1; b2 < 4; ++b2)
@@ -385,13 +396,14 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     std::vector<char> done((size_t)nfilt, 0);
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
-        const gsf::Dims dd = to_dims(q.dims);
+        const gsf::Dims dd = to_dims(core_dims(q));   // the core: F, statistics, masks
+        const gsf::Halo h{q.dims.nx, q.dims.ny, q.dims.nz, q.halo[0], q.halo[1], q.halo[2]};
         const gsf::Store sto = to_store(q.dtype);
         std::fill(done.begin(), done.end(), 0);
         for (int32_t g = 0; g < nfilt; ++g) {
             if (done[g]) continue;
             const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
-            hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, tz, s);
+            hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, h, tz, s);
             if (e != hipSuccess) return device_status(e, "gsf_find launch");
             for (int32_t j = g; j < nfilt; ++j) {
                 if (done[j] || f[j].sigma_z != f[g].sigma_z || f[j].truncate != f[g].truncate)
@@ -401,7 +413,7 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                 void *F = (F_out && F_out[o]) ? F_out[o] : Fbuf;
                 const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
                 int nparts = 0;
-                e = gsf::launch_yx(T1, F, w.w1, sto, dd, txy, w.partials, &nparts, s);
+                e = gsf::launch_yx(T1, F, w.w1, sto, dd, h, txy, w.partials, &nparts, s);
                 if (e == hipSuccess)
                     e = nparts > 0 ? gsf::launch_mean_partials(w.partials, nparts, dd.voxels(),
                                                                w.shift, s)

@@ -66,17 +66,19 @@ __device__ __forceinline__ void store4(St *p, const float (&v)[4])
 
 template <int R, typename St>
 __global__ __launch_bounds__(kThreads) void k_zpass_r(const St *__restrict__ in,
-                                                      St *__restrict__ out, int64_t nz, Taps t)
+                                                      St *__restrict__ out, int64_t nz,
+                                                      int64_t NZ, int64_t zoff, Taps t)
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
     __shared__ float4 tile4[kZOut / 4 + NW + 1];
     float *tile = reinterpret_cast<float *>(tile4);
     const int64_t row = blockIdx.x;
     const int64_t z0 = (int64_t)blockIdx.y * kZOut;
-    const St *src = in + row * nz;
+    // output z (core) reads input z + zoff of a row of NZ values
+    const St *src = in + row * NZ + zoff;
     for (int i = threadIdx.x; i < 4 * (kZOut / 4 + NW + 1); i += kThreads) {
         const int64_t z = z0 - R + i;
-        tile[i] = (z >= 0 && z < nz) ? widen(src[z]) : 0.0f;
+        tile[i] = (z + zoff >= 0 && z + zoff < NZ) ? widen(src[z]) : 0.0f;
     }
     __syncthreads();
     float w[4 * NW];
@@ -116,7 +118,8 @@ constexpr int kZRows = 16;
 template <int R, typename St>
 __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
                                                          St *__restrict__ out, int64_t nrows,
-                                                         int64_t nz, Taps t)
+                                                         int64_t nz, int64_t NZ, int64_t zoff,
+                                                         Taps t)
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
     constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
@@ -125,17 +128,20 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
     const int64_t r0 = (int64_t)blockIdx.x * kZRows;
     const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
     const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    // core z of the output maps to input z + zoff in rows of NZ values; all
+    // of nz, NZ and zoff are multiples of 4, so four values are all in or out
     const int64_t zm = z0 + 4 * tid;                 // this lane's four values and outputs
-    const bool mine = zm < nz;                       // nz % 4 == 0: all four or none
+    const bool mine = zm < nz;                       // outputs inside the core
+    const bool load = zm + zoff < NZ;                // inputs inside the array
     // halo: lanes 0 .. 2R-1 fetch z0 - R + lane (left) and z0 + kZOut + lane - R (right)
     const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
-    const bool halo = tid < 2 * R && zh >= 0 && zh < nz;
+    const bool halo = tid < 2 * R && zh + zoff >= 0 && zh + zoff < NZ;
     const int th = tid < R ? tid : kZOut + tid;      // its tile index
     float4 m = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float h = 0.0f;
     {
-        const St *row = in + r0 * nz;
-        if (mine) m = load4(row + zm);
+        const St *row = in + r0 * NZ + zoff;
+        if (load) m = load4(row + zm);
         if (halo) h = widen(row[zh]);
     }
     for (int64_t r = r0; r < r1; ++r) {
@@ -148,8 +154,8 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
         if (tid < 2 * R) tile[th] = h;
         __syncthreads();
         if (r + 1 < r1) {
-            const St *row = in + (r + 1) * nz;
-            m = mine ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const St *row = in + (r + 1) * NZ + zoff;
+            m = load ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
             h = halo ? widen(row[zh]) : 0.0f;
         }
         float w[4 * NW];
@@ -176,7 +182,8 @@ template <int R, int P, int NW, typename St>
 __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
                                                   St *__restrict__ F, int64_t nx, int64_t ny,
                                                   int64_t nz, int64_t xchunk, Taps t,
-                                                  double *__restrict__ partials)
+                                                  double *__restrict__ partials, int64_t NX,
+                                                  int64_t NY, int64_t hx, int64_t hy)
 {
     constexpr int L = 2 * R + 1;
     constexpr int TY = NW * P;            // output rows of the block
@@ -192,17 +199,21 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     const int64_t xa = (int64_t)blockIdx.z * xchunk;
     const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
     const bool zl = z < nz;
+    // T1 is NX x NY rows of nz (core z); F is the nx x ny x nz core, whose
+    // (x, y) reads T1 at (x + hx, y + hy)
     constexpr int64_t SZ = sizeof(St);
+    const int64_t tplane = NY * nz;
+    const uint32_t tplane_b = (uint32_t)(tplane * SZ);
     const int64_t plane = ny * nz;
     const uint32_t plane_b = (uint32_t)(plane * SZ);
     const uint32_t row_b = (uint32_t)(nz * SZ);
     // rows w, w + NW, ... of the block's TR-row window are this wave's to load;
-    // offsets wrap for rows above the cube and read 0 through the range check
+    // offsets wrap for rows above the array and read 0 through the range check
     uint32_t ldo[LW];
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
         const int tr = wave + i * NW;
-        ldo[i] = tr < TR ? (uint32_t)(((yb - R + tr) * nz + z) * SZ) : kOOB;
+        ldo[i] = tr < TR ? (uint32_t)(((yb + hy - R + tr) * nz + z) * SZ) : kOOB;
     }
     const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * SZ) : kOOB;
 
@@ -220,8 +231,9 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     // a plane outside [0, nx) gets an empty range, so its rows read 0
     // loads stay raw until stored to LDS two planes later
     auto load_plane = [&](int64_t xq, raw_t<St> (&r)[LW]) {
-        const bool in = xq >= 0 && xq < nx;
-        const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xq : 0) * plane, in ? plane_b : 0u);
+        const int64_t xt = xq + hx;                          // T1 plane of core plane xq
+        const bool in = xt >= 0 && xt < NX;
+        const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xt : 0) * tplane, in ? tplane_b : 0u);
 #pragma unroll
         for (int i = 0; i < LW; ++i) r[i] = sbuf_ld_raw<St>(rt, ldo[i]);
     };
@@ -315,27 +327,28 @@ const char *kernel_name(const char *base, int r)
 }
 
 template <int R, typename St>
-hipError_t zpass_r(const void *in_, void *out_, Dims d, const Taps &tz, hipStream_t s)
+hipError_t zpass_r(const void *in_, void *out_, Dims d, const Halo &h, const Taps &tz,
+                   hipStream_t s)
 {
     const St *in = (const St *)in_;
     St *out = (St *)out_;
-    const int64_t rows = d.nx * d.ny;
+    const int64_t rows = h.NX * h.NY;
     const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     prof::Scope scope(kernel_name<St>("k_zpass_r", R), s);
-    if (d.nz % 4 == 0) {
+    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0) {
         const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
         hipLaunchKernelGGL((k_zpass_rows<R, St>), grid, dim3(kThreads), 0, s, in, out, rows, d.nz,
-                           tz);
+                           h.NZ, (int64_t)h.hz, tz);
     } else {
         hipLaunchKernelGGL((k_zpass_r<R, St>), dim3((unsigned)rows, zt), dim3(kThreads), 0, s, in,
-                           out, d.nz, tz);
+                           out, d.nz, h.NZ, (int64_t)h.hz, tz);
     }
     return hipGetLastError();
 }
 
 template <int R, int P, int NW, typename St>
-hipError_t yx_r(const void *T, void *F, Dims d, const Taps &txy, double *partials, int *nparts,
-                hipStream_t s)
+hipError_t yx_r(const void *T, void *F, Dims d, const Halo &h, const Taps &txy, double *partials,
+                int *nparts, hipStream_t s)
 {
     const int64_t tz = (d.nz + 63) / 64;
     const int64_t ty = (d.ny + NW * P - 1) / (NW * P);
@@ -353,13 +366,14 @@ hipError_t yx_r(const void *T, void *F, Dims d, const Taps &txy, double *partial
     if (nparts) *nparts = partials ? (int)blocks : 0;
     prof::Scope scope(kernel_name<St>("k_yx_r", R), s);
     hipLaunchKernelGGL((k_yx_r<R, P, NW, St>), grid, dim3(64 * NW), 0, s, (const St *)T, (St *)F,
-                       d.nx, d.ny, d.nz, xchunk, txy, partials);
+                       d.nx, d.ny, d.nz, xchunk, txy, partials, h.NX, h.NY, (int64_t)h.hx,
+                       (int64_t)h.hy);
     return hipGetLastError();
 }
 
-using ZFn = hipError_t (*)(const void *, void *, Dims, const Taps &, hipStream_t);
-using YXFn = hipError_t (*)(const void *, void *, Dims, const Taps &, double *, int *,
-                            hipStream_t);
+using ZFn = hipError_t (*)(const void *, void *, Dims, const Halo &, const Taps &, hipStream_t);
+using YXFn = hipError_t (*)(const void *, void *, Dims, const Halo &, const Taps &, double *,
+                            int *, hipStream_t);
 
 template <typename St, int... R>
 const ZFn *ztab_of(std::integer_sequence<int, R...>)
@@ -388,27 +402,27 @@ bool zpass_fast(int rz) { return rz >= 1 && rz <= kMaxFastRz; }
 bool plane_fits(Dims d) { return d.ny * d.nz <= ((int64_t)1 << 28); }
 bool yx_fast(int rxy, Dims d) { return rxy >= 1 && rxy <= kMaxFastRxy && plane_fits(d); }
 
-hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Taps &tz,
-                             hipStream_t s)
+hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Halo &h,
+                             const Taps &tz, hipStream_t s)
 {
     if (!zpass_fast(tz.r)) return hipErrorInvalidValue;
     const auto seq = std::make_integer_sequence<int, kMaxFastRz>{};
     switch (st) {
-    case Store::F16: return ztab_of<_Float16>(seq)[tz.r](in, T1, d, tz, s);
-    case Store::BF16: return ztab_of<__bf16>(seq)[tz.r](in, T1, d, tz, s);
-    default: return ztab_of<float>(seq)[tz.r](in, T1, d, tz, s);
+    case Store::F16: return ztab_of<_Float16>(seq)[tz.r](in, T1, d, h, tz, s);
+    case Store::BF16: return ztab_of<__bf16>(seq)[tz.r](in, T1, d, h, tz, s);
+    default: return ztab_of<float>(seq)[tz.r](in, T1, d, h, tz, s);
     }
 }
 
-hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Taps &txy,
-                          double *partials, int *nparts, hipStream_t s)
+hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,
+                          const Taps &txy, double *partials, int *nparts, hipStream_t s)
 {
-    if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
+    if (!yx_fast(txy.r, d) || !yx_fast(txy.r, Dims{h.NX, h.NY, d.nz})) return hipErrorInvalidValue;
     const auto seq = std::make_integer_sequence<int, kMaxFastRxy>{};
     switch (st) {
-    case Store::F16: return yxtab_of<_Float16>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
-    case Store::BF16: return yxtab_of<__bf16>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
-    default: return yxtab_of<float>(seq)[txy.r](T1, F, d, txy, partials, nparts, s);
+    case Store::F16: return yxtab_of<_Float16>(seq)[txy.r](T1, F, d, h, txy, partials, nparts, s);
+    case Store::BF16: return yxtab_of<__bf16>(seq)[txy.r](T1, F, d, h, txy, partials, nparts, s);
+    default: return yxtab_of<float>(seq)[txy.r](T1, F, d, h, txy, partials, nparts, s);
     }
 }
 

@@ -35,6 +35,16 @@ struct Dims {
     int64_t words() const { return nx * ny * ((nz + 63) / 64); }
 };
 
+// Input array of the filter and the core it produces: the array is NX x NY x
+// NZ, the core (dims passed alongside as Dims) starts at (hx, hy, hz).  The
+// spectral pass writes T1 as NX x NY rows of the core's nz values.
+struct Halo {
+    int64_t NX, NY, NZ;
+    int hx, hy, hz;
+};
+
+inline Halo no_halo(Dims d) { return Halo{d.nx, d.ny, d.nz, 0, 0, 0}; }
+
 // Window of length B: offsets [lo, lo + B - 1] with lo = -floor(B/2).
 struct Box {
     int bx, by, bz;
@@ -67,10 +77,10 @@ bool zpass_fast(int rz);
 // Buffer-addressed kernels need one x-plane below 2^30 bytes.
 bool plane_fits(Dims d);
 bool yx_fast(int rxy, Dims d);
-hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Taps &tz,
-                             hipStream_t s);
-hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Taps &txy,
-                          double *partials, int *nparts, hipStream_t s);
+hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Halo &h,
+                             const Taps &tz, hipStream_t s);
+hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,
+                          const Taps &txy, double *partials, int *nparts, hipStream_t s);
 
 // Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
 // bx in {8, 16, 32, 64}, bz <= 65.  ws G1, G2: two cubes of floats.
@@ -81,14 +91,15 @@ hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const doubl
 
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
 // Cubes passed as void * hold elements of storage type st.
-// Spectral pass: T1 = gz * in along z.
-hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Taps &tz,
-                        hipStream_t s);
-// Spatial passes: F = gxy * (gxy * T1 along y) along x.  tmp is a scratch
-// cube used only by the generic path.  If partials is non-null, per-block
-// FP64 sums of F may be written there; *nparts gets their count (0 if not).
-hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Taps &txy,
-                     double *partials, int *nparts, hipStream_t s);
+// Spectral pass: T1 = gz * in along z.  d: the core; h: the input array.
+hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Halo &h,
+                        const Taps &tz, hipStream_t s);
+// Spatial passes: F = gxy * (gxy * T1 along y) along x, F of the core dims d.
+// tmp is a scratch cube (NX x ny x nz) used only by the generic path.  If
+// partials is non-null, per-block FP64 sums of F may be written there;
+// *nparts gets their count (0 if not).
+hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Halo &h,
+                     const Taps &txy, double *partials, int *nparts, hipStream_t s);
 // shift[0] = mean of F (FP64), full pass over F with a fixed reduction order.
 hipError_t launch_mean(const void *F, Store st, Dims d, double *partials, double *shift,
                        hipStream_t s);

@@ -22,16 +22,18 @@ constexpr int kBlock = 256;   // four wave64s along z
 // with coalesced loads, then every lane reads its 2r+1 neighbours from LDS.
 template <typename St>
 __global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
-                                                  St *__restrict__ out, int64_t nz, Taps t)
+                                                  St *__restrict__ out, int64_t nz, int64_t NZ,
+                                                  int64_t zoff, Taps t)
 {
     extern __shared__ float tile[];
     const int r = t.r;
     const int64_t row = blockIdx.x;
     const int64_t z0 = (int64_t)blockIdx.y * kBlock;
-    const St *src = in + row * nz;
+    // output z (core, nz per row) reads input z + zoff (NZ per row)
+    const St *src = in + row * NZ + zoff;
     for (int i = threadIdx.x; i < kBlock + 2 * r; i += kBlock) {
         const int64_t z = z0 - r + i;
-        tile[i] = (z >= 0 && z < nz) ? widen(src[z]) : 0.0f;
+        tile[i] = (z + zoff >= 0 && z + zoff < NZ) ? widen(src[z]) : 0.0f;
     }
     __syncthreads();
     const int64_t z = z0 + threadIdx.x;
@@ -42,26 +44,27 @@ __global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
     }
 }
 
-// Pass along a strided axis (y: stride nz, x: stride ny*nz).  Lanes run
-// along z so every tap load is a coalesced row read.
+// Pass along a strided axis.  Output row (X, y) of NYo rows per plane reads
+// input rows of NYi rows per plane: along y, input row y + off + o of plane X
+// (inside [0, NYi)); along x, row y of plane X + off + o (inside [0, NXi)).
+// Lanes run along z so every tap load is a coalesced row read.
 template <typename St>
 __global__ __launch_bounds__(kBlock) void k_strided_pass(const St *__restrict__ in,
-                                                         St *__restrict__ out, int64_t ny,
-                                                         int64_t nz, int axis_x, int64_t n_axis,
-                                                         Taps t)
+                                                         St *__restrict__ out, int64_t NXi,
+                                                         int64_t NYi, int64_t NYo, int64_t nz,
+                                                         int axis_x, int64_t off, Taps t)
 {
     const int r = t.r;
-    const int64_t row = blockIdx.x;          // x*ny + y
+    const int64_t row = blockIdx.x;          // X*NYo + y
     const int64_t z = (int64_t)blockIdx.y * kBlock + threadIdx.x;
     if (z >= nz) return;
-    const int64_t y = row % ny, x = row / ny;
-    const int64_t pos = axis_x ? x : y;
-    const int64_t stride = axis_x ? ny * nz : nz;
-    const St *src = in + row * nz + z;
+    const int64_t y = row % NYo, X = row / NYo;
     float acc = 0.0f;
     for (int o = -r; o <= r; ++o) {
-        const int64_t p = pos + o;
-        if (p >= 0 && p < n_axis) acc = fmaf(t.g[o + r], widen(src[(int64_t)o * stride]), acc);
+        const int64_t xi = axis_x ? X + off + o : X;
+        const int64_t yi = axis_x ? y : y + off + o;
+        if (xi >= 0 && xi < NXi && yi >= 0 && yi < NYi)
+            acc = fmaf(t.g[o + r], widen(in[(xi * NYi + yi) * nz + z]), acc);
     }
     out[row * nz + z] = narrow<St>(acc);
 }
@@ -268,36 +271,41 @@ inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Taps &tz, hipStream_t s)
+hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Halo &h,
+                        const Taps &tz, hipStream_t s)
 {
-    if (zpass_fast(tz.r)) return launch_zpass_fast(in, T1, st, d, tz, s);
-    const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
+    if (zpass_fast(tz.r)) return launch_zpass_fast(in, T1, st, d, h, tz, s);
+    const dim3 grid((unsigned)(h.NX * h.NY), ztiles(d.nz));
     prof::Scope scope_("k_zpass", s);
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
         hipLaunchKernelGGL(k_zpass<St>, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s,
-                           (const St *)in, (St *)T1, d.nz, tz);
+                           (const St *)in, (St *)T1, d.nz, h.NZ, (int64_t)h.hz, tz);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Taps &txy,
-                     double *partials, int *nparts, hipStream_t s)
+hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const Halo &h,
+                     const Taps &txy, double *partials, int *nparts, hipStream_t s)
 {
-    if (yx_fast(txy.r, d)) return launch_yx_fast(T1, F, st, d, txy, partials, nparts, s);
+    if (yx_fast(txy.r, d) && yx_fast(txy.r, Dims{h.NX, h.NY, d.nz}))
+        return launch_yx_fast(T1, F, st, d, h, txy, partials, nparts, s);
     if (nparts) *nparts = 0;
-    const dim3 grid((unsigned)(d.nx * d.ny), ztiles(d.nz));
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
         {
+            // y pass: T1 (NX x NY rows) -> tmp (NX x ny rows)
             prof::Scope scope_("k_strided_pass", s);
-            hipLaunchKernelGGL(k_strided_pass<St>, grid, dim3(kBlock), 0, s, (const St *)T1,
-                               (St *)tmp, d.ny, d.nz, 0, d.ny, txy);
+            hipLaunchKernelGGL(k_strided_pass<St>, dim3((unsigned)(h.NX * d.ny), ztiles(d.nz)),
+                               dim3(kBlock), 0, s, (const St *)T1, (St *)tmp, h.NX, h.NY, d.ny,
+                               d.nz, 0, (int64_t)h.hy, txy);
         }
         {
+            // x pass: tmp (NX x ny rows) -> F (nx x ny rows)
             prof::Scope scope_("k_strided_pass", s);
-            hipLaunchKernelGGL(k_strided_pass<St>, grid, dim3(kBlock), 0, s, (const St *)tmp,
-                               (St *)F, d.ny, d.nz, 1, d.nx, txy);
+            hipLaunchKernelGGL(k_strided_pass<St>, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)),
+                               dim3(kBlock), 0, s, (const St *)tmp, (St *)F, h.NX, d.ny, d.ny,
+                               d.nz, 1, (int64_t)h.hx, txy);
         }
         return hipGetLastError();
     });

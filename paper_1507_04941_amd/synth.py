@@ -67,6 +67,58 @@ LARGE = Workload(
 WORKLOADS = {w.name: w for w in (SMALL, LARGE)}
 
 
+@dataclass(frozen=True)
+class BatchWorkload:
+    """A batch of uneven sub-cubes, each a core plus an input-only halo.
+
+    Core sizes: nx, ny ~ U{lo_xy..hi_xy}, nz ~ U{lo_z..hi_z} drawn in cube
+    order from PCG64(size_seed); cube i is make_cube(core + 2*halo,
+    round(V_core / 2^17) sources, seed cube_seed + i).  The halo (per side)
+    is 3 x the largest sigma of the bank along each axis."""
+    name: str
+    n_cubes: int
+    core_xy: tuple[int, int]
+    core_z: tuple[int, int]
+    halo: tuple[int, int, int]
+    size_seed: int
+    cube_seed: int
+    filters: tuple[tuple[float, float], ...]
+    box: tuple[int, int, int]
+    k: float = 4.0
+
+
+BATCH = BatchWorkload(
+    name="batch96_core48-256x48-256x64-1024_halo12-12-24_f6_box64",
+    n_cubes=96,
+    core_xy=(48, 256),
+    core_z=(64, 1024),
+    halo=(12, 12, 24),
+    size_seed=999,
+    cube_seed=1000,
+    filters=LARGE.filters,
+    box=LARGE.box,
+)
+
+
+def batch_cores(b: BatchWorkload) -> list[tuple[int, int, int]]:
+    rng = np.random.Generator(np.random.PCG64(b.size_seed))
+    cores = []
+    for _ in range(b.n_cubes):
+        nx = int(rng.integers(b.core_xy[0], b.core_xy[1] + 1))
+        ny = int(rng.integers(b.core_xy[0], b.core_xy[1] + 1))
+        nz = int(rng.integers(b.core_z[0], b.core_z[1] + 1))
+        cores.append((nx, ny, nz))
+    return cores
+
+
+def batch_cube(b: BatchWorkload, i: int) -> np.ndarray:
+    """Sub-cube i of the batch: the full array (core plus halo), FP32."""
+    core = batch_cores(b)[i]
+    shape = tuple(c + 2 * h for c, h in zip(core, b.halo))
+    n_src = int(round(core[0] * core[1] * core[2] / 2.0 ** 17))
+    return make_cube(shape, n_src, b.cube_seed + i)
+
+
 def _add_source(cube: np.ndarray, x0: float, y0: float, z0: float, amp: float,
                 s_xy: float, s_z: float) -> None:
     nx, ny, nz = cube.shape

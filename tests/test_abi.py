@@ -129,8 +129,8 @@ def test_find_validation(L):
     assert L.gsf_find(cubes, 1, filt, 0, box, 4.0, masks, None, None, None, ws, need, None) == 1
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, None, None, None, None, ws, need, None) == 1
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need - 1, None) == 3
-    cubes[0].halo[2] = 2
-    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 2
+    cubes[0].halo[2] = 4   # 8 - 2*4: no core left
+    assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
     cubes[0].halo[2] = -1
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks, None, None, None, ws, need, None) == 1
     cubes[0].halo[2] = 0
