@@ -139,7 +139,9 @@ gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const fl
 
 /* ---- The whole path over a batch of cubes and a filter bank ---- */
 
-/* Bytes of device workspace gsf_find needs for this batch.  Pure host. */
+/* Bytes of device workspace gsf_find needs for this batch: one slot per
+ * concurrently processed cube (min(ncubes, 4)), each sized for the batch's
+ * largest array.  Pure host. */
 gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
                                    int32_t nfilt, gsf_box b, size_t *bytes);
 
@@ -152,7 +154,15 @@ gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const 
  * mean and local std (floats).  A cube may be stored as GSF_F32, GSF_F16 or
  * GSF_BF16; its spectral-pass intermediate and F are then stored in that
  * type, the window sums stay FP32.  ws: at least gsf_find_workspace_size
- * bytes (sized for FP32, enough for every storage type). */
+ * bytes (sized for FP32, enough for every storage type).
+ * Cubes are independent: with more than one cube the call forks `stream`
+ * into up to 4 library-owned streams (created on first use per device, kept
+ * until the process ends, default priority), gives each its own slice of ws,
+ * runs the largest cubes first on the least loaded stream, and makes
+ * `stream` wait for all of them before returning (also after an error), so
+ * the results are ordered on `stream` as for one cube.  Such calls from
+ * several host threads are serialized while they enqueue.  Every cube's
+ * results are identical to those of a call with that cube alone. */
 gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
                     gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
                     float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,

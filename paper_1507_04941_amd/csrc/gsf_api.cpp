@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -326,8 +328,49 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
     return GSF_OK;
 }
 
-// [T1][F scratch][statistics workspace]
-size_t find_ws(gsf_dims largest) { return 2 * cube_bytes(largest) + stats_ws(largest); }
+// Independent cubes of a batch run concurrently on up to kSlots library
+// streams forked from the caller's stream, each with its own workspace slot
+// [T1][F scratch][statistics workspace]; a single cube runs on the caller's
+// stream.
+constexpr int kSlots = 4;
+
+int find_slots(int32_t ncubes) { return ncubes < kSlots ? ncubes : kSlots; }
+
+size_t slot_ws(gsf_dims largest) { return 2 * cube_bytes(largest) + stats_ws(largest); }
+
+size_t find_ws(gsf_dims largest, int32_t ncubes)
+{
+    return (size_t)find_slots(ncubes) * slot_ws(largest);
+}
+
+// Library streams and fork/join events of one device, created on first use
+// and kept until the process ends.  Streams have the default priority.
+struct SlotStreams {
+    hipStream_t stream[kSlots];
+    hipEvent_t fork;
+    hipEvent_t join[kSlots];
+};
+
+std::mutex g_slots_mu;
+std::map<int, SlotStreams> g_slots;
+
+gsf_status slot_streams(SlotStreams **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GSF_ERR_DEVICE, "hipGetDevice failed");
+    auto it = g_slots.find(dev);
+    if (it == g_slots.end()) {
+        SlotStreams ss{};
+        bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < kSlots && good; ++i)
+            good = hipStreamCreateWithFlags(&ss.stream[i], hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+        if (!good) return fail(GSF_ERR_DEVICE, "creating the batch streams failed");
+        it = g_slots.emplace(dev, ss).first;
+    }
+    *out = &it->second;
+    return GSF_OK;
+}
 
 }  // namespace
 
@@ -338,7 +381,7 @@ gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const 
     gsf_dims largest{};
     if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
     if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
-    *bytes = find_ws(largest);
+    *bytes = find_ws(largest, ncubes);
     return ok();
 }
 
@@ -352,7 +395,7 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
     if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
     if (!masks) return fail(GSF_ERR_INVALID_ARG, "masks is NULL");
-    const size_t need = find_ws(largest);
+    const size_t need = find_ws(largest, ncubes);
     if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((st = check_ptr(ws, 16, "ws"))) return st;
     // Validate every output pointer before enqueueing anything.
@@ -386,15 +429,44 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
             }
         }
     }
-    const hipStream_t s = (hipStream_t)stream;
-    char *base = (char *)ws;
-    void *T1 = base;                              // in the cube's storage type
-    void *Fbuf = base + cube_bytes(largest);
-    const StatsWs w = carve_stats(base + 2 * cube_bytes(largest), largest);
+    // Largest cubes first, each to the slot with the least work so far.
+    const int nslots = find_slots(ncubes);
+    std::vector<int32_t> order((size_t)ncubes);
+    for (int32_t c = 0; c < ncubes; ++c) order[(size_t)c] = c;
+    auto vox = [&](int32_t c) { return cubes[c].dims.nx * cubes[c].dims.ny * cubes[c].dims.nz; };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b2) { return vox(a) > vox(b2); });
+    std::vector<int> slot_of((size_t)ncubes, 0);
+    std::vector<int64_t> load((size_t)nslots, 0);
+    for (int32_t c : order) {
+        const int sl = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        slot_of[(size_t)c] = sl;
+        load[(size_t)sl] += vox(c);
+    }
+    const hipStream_t caller = (hipStream_t)stream;
+    std::unique_lock<std::mutex> lock(g_slots_mu, std::defer_lock);
+    SlotStreams *ss = nullptr;
+    if (nslots > 1) {
+        lock.lock();
+        if ((st = slot_streams(&ss))) return st;
+        if (hipEventRecord(ss->fork, caller) != hipSuccess)
+            return fail(GSF_ERR_DEVICE, "gsf_find: fork event failed");
+        for (int i = 0; i < nslots; ++i)
+            if (hipStreamWaitEvent(ss->stream[i], ss->fork, 0) != hipSuccess)
+                return fail(GSF_ERR_DEVICE, "gsf_find: fork wait failed");
+    }
+    const size_t sws = slot_ws(largest);
     // The spectral pass depends only on (sigma_z, truncate): run it once per
     // distinct pair and apply every filter that shares it.
     std::vector<char> done((size_t)nfilt, 0);
-    for (int32_t c = 0; c < ncubes; ++c) {
+    const gsf_status run = [&]() -> gsf_status {
+    for (int32_t c : order) {
+        const int sl = slot_of[(size_t)c];
+        const hipStream_t s = nslots > 1 ? ss->stream[sl] : caller;
+        char *base = (char *)ws + (size_t)sl * sws;
+        void *T1 = base;                              // in the cube's storage type
+        void *Fbuf = base + cube_bytes(largest);
+        const StatsWs w = carve_stats(base + 2 * cube_bytes(largest), largest);
         const gsf_cube &q = cubes[c];
         const gsf::Dims dd = to_dims(core_dims(q));   // the core: F, statistics, masks
         const gsf::Halo h{q.dims.nx, q.dims.ny, q.dims.nz, q.halo[0], q.halo[1], q.halo[2]};
@@ -426,7 +498,16 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
             }
         }
     }
-    return ok();
+    return GSF_OK;
+    }();
+    if (nslots > 1) {
+        // join, also after a failed launch: the caller's stream waits for every slot
+        for (int i = 0; i < nslots; ++i)
+            if (hipEventRecord(ss->join[i], ss->stream[i]) != hipSuccess ||
+                hipStreamWaitEvent(caller, ss->join[i], 0) != hipSuccess)
+                return fail(GSF_ERR_DEVICE, "gsf_find: join failed");
+    }
+    return run != GSF_OK ? run : ok();
 }
 
 }  // extern "C"
