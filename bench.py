@@ -146,6 +146,8 @@ def main() -> int:
                     help="skip the FP16/BF16-storage timings")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch of 96 halo sub-cubes")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the serving run (Poisson, 200/s); 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -265,6 +267,30 @@ def main() -> int:
         print(f"# batch: {tb:.2f} ms per call", file=sys.stderr, flush=True)
         del pb, cubes
 
+    # the serving form: Poisson arrivals of lognormal-volume sub-cubes,
+    # four streams, 200 GB budget, device-resident F/mean/std
+    serving = None
+    if args.serve_requests > 0:
+        from paper_1507_04941_amd import serve
+        arr = serve.Arrivals()
+        serving = {"arrivals": f"Poisson {arr.rate_per_s:g}/s, lognormal volume median 2^22, "
+                               f"clip [2^15, 2^28], nz = 2 nx = 2 ny",
+                   "requests": args.serve_requests}
+        for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
+            t_arr, shapes = arr.draw(args.serve_requests)
+            reqs = [serve.Request(j, float(t_arr[j]),
+                                  serve.device_noise(shapes[j], arr.cube_seed + j, dev, dt))
+                    for j in range(args.serve_requests)]
+            big = max(reqs, key=lambda r: r.voxels).cube.shape
+            srv = serve.Server(w.filters, w.box, w.k, lanes=4, max_shape=big, device=dev, dtype=dt)
+            srv.run(reqs)                                   # warm the allocator
+            st = srv.run(reqs)
+            serving[name] = {k: round(v, 3) for k, v in st.items() if isinstance(v, float)}
+            print(f"# serving {name}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms",
+                  file=sys.stderr, flush=True)
+            del reqs, srv
+            torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, d, args.cpu_seconds)
@@ -291,6 +317,7 @@ def main() -> int:
         "kernels": kernels,
         "storage16": storage16 or None,
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     return 0
