@@ -54,6 +54,8 @@ def _load():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [_ptr, _i64, _i64, _i64, _dbl, _dbl, _dbl, _ptr]
+    lib.oracle_filter3d_weighted.restype = ctypes.c_int
+    lib.oracle_filter3d_weighted.argtypes = [_ptr, _ptr, _i64, _i64, _i64, _dbl, _dbl, _dbl, _ptr]
     lib.oracle_filter3d_direct_at.restype = ctypes.c_int
     lib.oracle_filter3d_direct_at.argtypes = [_ptr, _i64, _i64, _i64, _dbl, _dbl, _dbl,
                                               _ptr, _i64, _ptr]
@@ -129,6 +131,20 @@ def filter3d(d, sigma_xy: float, sigma_z: float, truncate: float = 3.0) -> np.nd
                                  float(truncate), _p(F))
     if rc:
         raise RuntimeError(f"oracle_filter3d failed ({rc})")
+    return F
+
+
+def filter3d_weighted(d, w, sigma_xy: float, sigma_z: float, truncate: float = 3.0) -> np.ndarray:
+    """Eq. 1 (§2.1), the weighted convolution, read as sum(d w f) / sum(w f)
+    over the support (zero outside the cube); 0 where the denominator is 0."""
+    d = _f32(d)
+    w = _f32(w)
+    if w.shape != d.shape:
+        raise ValueError("weights must have the cube's shape")
+    F = np.empty(d.shape, dtype=np.float64)
+    if _load().oracle_filter3d_weighted(_p(d), _p(w), *d.shape, float(sigma_xy), float(sigma_z),
+                                        float(truncate), _p(F)):
+        raise RuntimeError("oracle_filter3d_weighted failed")
     return F
 
 

@@ -39,6 +39,34 @@ def conv3d(d: np.ndarray, sigma_xy: float, sigma_z: float, truncate: float = 3.0
     return out
 
 
+def conv3d_weighted(d: np.ndarray, w: np.ndarray, sigma_xy: float, sigma_z: float,
+                    truncate: float = 3.0) -> np.ndarray:
+    """Eq. 1 read as sum(d w f) / sum(w f) over the explicit 3-D support, 0
+    where the denominator is 0."""
+    d = np.asarray(d, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    gxy = gaussian_taps(sigma_xy, truncate)
+    gz = gaussian_taps(sigma_z, truncate)
+    rxy, rz = len(gxy) // 2, len(gz) // 2
+    f = gxy[:, None, None] * gxy[None, :, None] * gz[None, None, :]
+    nx, ny, nz = d.shape
+    out = np.zeros(d.shape)
+    for x in range(nx):
+        for y in range(ny):
+            for z in range(nz):
+                num = den = 0.0
+                for ox in range(-rxy, rxy + 1):
+                    for oy in range(-rxy, rxy + 1):
+                        for oz in range(-rz, rz + 1):
+                            ix, iy, iz = x + ox, y + oy, z + oz
+                            if 0 <= ix < nx and 0 <= iy < ny and 0 <= iz < nz:
+                                fw = f[ox + rxy, oy + rxy, oz + rz] * w[ix, iy, iz]
+                                num += d[ix, iy, iz] * fw
+                                den += fw
+                out[x, y, z] = num / den if den != 0.0 else 0.0
+    return out
+
+
 def window_bounds(i: int, n: int, B: int) -> tuple[int, int]:
     lo = i - B // 2
     return max(lo, 0), min(lo + B, n)

@@ -125,8 +125,9 @@ int oracle_filter3d_direct(const float *d, int64_t nx, int64_t ny, int64_t nz,
 /* Eq. 2 as three 1-D passes (z, then y, then x), each a sum over the taps in
  * order -r..r with zero outside the cube.  The triple sum factorises because
  * f[ox][oy][oz] = gxy[ox] * gxy[oy] * gz[oz]. */
-int oracle_filter3d(const float *d, int64_t nx, int64_t ny, int64_t nz,
-                    double sigma_xy, double sigma_z, double truncate, double *F)
+/* Eq. 2 as z, y and x passes over an FP64 input array (zero outside). */
+static int filter3d_f64(const double *d, int64_t nx, int64_t ny, int64_t nz, double sigma_xy,
+                        double sigma_z, double truncate, double *F)
 {
     double gxy[ORACLE_MAX_TAPS], gz[ORACLE_MAX_TAPS];
     int rxy = oracle_taps(sigma_xy, truncate, gxy, ORACLE_MAX_TAPS);
@@ -140,13 +141,13 @@ int oracle_filter3d(const float *d, int64_t nx, int64_t ny, int64_t nz,
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t x = 0; x < nx; ++x)
         for (int64_t y = 0; y < ny; ++y) {
-            const float *row = d + (x * ny + y) * nz;
+            const double *row = d + (x * ny + y) * nz;
             double *o = F + (x * ny + y) * nz;
             for (int64_t z = 0; z < nz; ++z) {
                 double c = 0.0;
                 for (int oz = -rz; oz <= rz; ++oz) {
                     int64_t iz = z + oz;
-                    if (iz >= 0 && iz < nz) c += (double)row[iz] * gz[oz + rz];
+                    if (iz >= 0 && iz < nz) c += row[iz] * gz[oz + rz];
                 }
                 o[z] = c;
             }
@@ -185,9 +186,51 @@ int oracle_filter3d(const float *d, int64_t nx, int64_t ny, int64_t nz,
     return 0;
 }
 
-/* Window of box length B around index i: [i - floor(B/2), i - floor(B/2) + B - 1],
- * clipped to [0, n-1].  Returns the clipped length; *a and *b get the
- * half-open clipped range [a, b). */
+/* Eq. 2 of an FP32 cube: the values promoted exactly to FP64. */
+int oracle_filter3d(const float *d, int64_t nx, int64_t ny, int64_t nz,
+                    double sigma_xy, double sigma_z, double truncate, double *F)
+{
+    const int64_t n = nx * ny * nz;
+    double *D = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!D) return -2;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) D[i] = (double)d[i];
+    int rc = filter3d_f64(D, nx, ny, nz, sigma_xy, sigma_z, truncate, F);
+    free(D);
+    return rc;
+}
+
+/* Eq. 1, the weighted convolution, read as a normalised convolution:
+ * F = sum(d w f) / sum(w f) over the filter support (zero outside the cube),
+ * i.e. Eq. 2 of the product d*w over Eq. 2 of w; F = 0 where the denominator
+ * is 0.  The products of the FP32 inputs are exact in FP64. */
+int oracle_filter3d_weighted(const float *d, const float *w, int64_t nx, int64_t ny, int64_t nz,
+                             double sigma_xy, double sigma_z, double truncate, double *F)
+{
+    const int64_t n = nx * ny * nz;
+    double *P = (double *)malloc(sizeof(double) * (size_t)n);
+    double *W = (double *)malloc(sizeof(double) * (size_t)n);
+    double *den = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = (P && W && den) ? 0 : -2;
+    if (!rc) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            P[i] = (double)d[i] * (double)w[i];
+            W[i] = (double)w[i];
+        }
+        rc = filter3d_f64(P, nx, ny, nz, sigma_xy, sigma_z, truncate, F);
+        if (!rc) rc = filter3d_f64(W, nx, ny, nz, sigma_xy, sigma_z, truncate, den);
+        if (!rc) {
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < n; ++i) F[i] = den[i] != 0.0 ? F[i] / den[i] : 0.0;
+        }
+    }
+    free(P);
+    free(W);
+    free(den);
+    return rc;
+}
+
 static int64_t window(int64_t i, int64_t n, int B, int64_t *a, int64_t *b)
 {
     int64_t lo = i - (int64_t)(B / 2);
