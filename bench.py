@@ -242,6 +242,33 @@ def main() -> int:
             print(f"# {name} storage: {t16:.3f} ms/step", file=sys.stderr, flush=True)
             del p16, c16
 
+    # the weighted convolution (Eq. 1) of the same cube, one filter, random weights
+    weighted = None
+    if not args.no_batch:
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        wts = torch.rand(cube.shape, generator=g, device=dev) + 0.5
+        fw = w.filters[3]
+        outw = torch.empty_like(cube)
+        n = B._SZ(0)
+        B._check(B.lib().gsf_filter3d_weighted_workspace_size(B._dims(cube.shape),
+                                                              B.ctypes.byref(B._filter(fw)),
+                                                              B.ctypes.byref(n)))
+        wsw = torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            B.filter3d_weighted(cube, wts, fw, out=outw, ws=wsw)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            B.filter3d_weighted(cube, wts, fw, out=outw, ws=wsw)
+        e1.record()
+        torch.cuda.synchronize()
+        tw = e0.elapsed_time(e1) / args.steps
+        weighted = {"filter": list(fw), "ms_per_call": round(tw, 3),
+                    "value": round(V / (tw * 1e-3) / 1e9, 3), "unit": "GVoxel-filters/s"}
+        print(f"# weighted: {tw:.3f} ms per call", file=sys.stderr, flush=True)
+        del wts, outw, wsw
+
     # the batched form: 96 uneven sub-cubes with halos in one gsf_find call
     batch = None
     if not args.no_batch:
@@ -317,6 +344,7 @@ def main() -> int:
         "kernels": kernels,
         "storage16": storage16 or None,
         "batch": batch,
+        "weighted": weighted,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

@@ -113,6 +113,22 @@ gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *
 gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_filter *f,
                         void *out, gsf_dtype out_t, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Weighted filtering: Eq. 1 (§2.1) ---- */
+
+/* Bytes of device workspace gsf_filter3d_weighted needs.  Pure host. */
+gsf_status gsf_filter3d_weighted_workspace_size(gsf_dims d, const gsf_filter *f, size_t *bytes);
+
+/* out = Eq. 1, the weighted convolution of `in` with weights `w`, read as the
+ * normalised convolution out = sum(d w f) / sum(w f) over the filter support
+ * (zero outside the cube), so that unit weights give Eq. 2 away from the
+ * faces; out = 0 where sum(w f) = 0.  in, w, out: nx*ny*nz elements of t
+ * (GSF_F32 only; others return GSF_ERR_UNSUPPORTED); none may overlap
+ * another or ws.  Computed as Eq. 2 of d*w (FP32 product) over Eq. 2 of w,
+ * FP32 arithmetic. */
+gsf_status gsf_filter3d_weighted(const void *in, const void *w, gsf_dtype t, gsf_dims d,
+                                 const gsf_filter *f, void *out, void *ws, size_t ws_bytes,
+                                 void *stream);
+
 /* ---- Local statistics: §3.3, mean and std over a range around each voxel ---- */
 
 /* Bytes of device workspace gsf_local_stats needs.  Pure host computation. */

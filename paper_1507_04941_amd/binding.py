@@ -59,6 +59,10 @@ SIGNATURES = [
     ("gsf_filter3d_workspace_size", _ST, [Dims, ctypes.POINTER(Filter), ctypes.POINTER(_SZ)]),
     ("gsf_filter3d", _ST, [_P, ctypes.c_int, Dims, ctypes.POINTER(Filter), _P, ctypes.c_int, _P,
                            _SZ, _P]),
+    ("gsf_filter3d_weighted_workspace_size", _ST, [Dims, ctypes.POINTER(Filter),
+                                                   ctypes.POINTER(_SZ)]),
+    ("gsf_filter3d_weighted", _ST, [_P, _P, ctypes.c_int, Dims, ctypes.POINTER(Filter), _P, _P,
+                                    _SZ, _P]),
     ("gsf_local_stats_workspace_size", _ST, [Dims, Box, ctypes.POINTER(_SZ)]),
     ("gsf_local_stats", _ST, [_P, ctypes.c_int, Dims, Box, _P, _P, _P, _SZ, _P]),
     ("gsf_threshold", _ST, [_P, ctypes.c_int, _P, _P, Dims, ctypes.c_double, _P, _P]),
@@ -189,6 +193,26 @@ def filter3d(cube: torch.Tensor, f, out: torch.Tensor | None = None,
     _check(lib().gsf_filter3d(cube.data_ptr(), gsf_dtype(cube), _dims(cube.shape),
                               ctypes.byref(_filter(f)), out.data_ptr(), gsf_dtype(out),
                               ws.data_ptr(), ws.numel(), _stream(cube.device)))
+    return out
+
+
+def filter3d_weighted(cube: torch.Tensor, w: torch.Tensor, f, out: torch.Tensor | None = None,
+                      ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Eq. 1: the weighted convolution sum(d w f) / sum(w f) (float32)."""
+    cube, w = _cube(cube, "cube"), _cube(w, "w")
+    if w.shape != cube.shape:
+        raise ValueError("weights must have the cube's shape")
+    if out is None:
+        out = torch.empty_like(cube)
+    _cube(out, "out")
+    n = _SZ(0)
+    _check(lib().gsf_filter3d_weighted_workspace_size(_dims(cube.shape), ctypes.byref(_filter(f)),
+                                                      ctypes.byref(n)))
+    if ws is None:
+        ws = torch.empty(int(n.value), dtype=torch.uint8, device=cube.device)
+    _check(lib().gsf_filter3d_weighted(cube.data_ptr(), w.data_ptr(), GSF_F32, _dims(cube.shape),
+                                       ctypes.byref(_filter(f)), out.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), _stream(cube.device)))
     return out
 
 

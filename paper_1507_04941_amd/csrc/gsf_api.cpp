@@ -164,6 +164,13 @@ size_t filter_ws(gsf_dims d, const gsf_filter *f)
     return cube_bytes(d) * (gsf::yx_fast(rxy, to_dims(d)) ? 1 : 2);
 }
 
+// gsf_filter3d_weighted: P = d*w, T1, D, plus the generic path's scratch cube.
+size_t weighted_ws(gsf_dims d, const gsf_filter *f)
+{
+    const int rxy = (int)std::ceil(f->truncate * f->sigma_xy);
+    return cube_bytes(d) * (gsf::yx_fast(rxy, to_dims(d)) ? 3 : 4);
+}
+
 gsf_status device_status(hipError_t e, const char *what)
 {
     if (e != hipSuccess)
@@ -235,6 +242,55 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
     hipError_t e = gsf::launch_zpass(in, T1, sto, dd, h, tz, s);
     if (e == hipSuccess) e = gsf::launch_yx(T1, out, tmp, sto, dd, h, txy, nullptr, nullptr, s);
     return device_status(e, "gsf_filter3d launch");
+}
+
+gsf_status gsf_filter3d_weighted_workspace_size(gsf_dims d, const gsf_filter *f, size_t *bytes)
+{
+    gsf_status st;
+    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_dims(d)) || (st = check_filter(f))) return st;
+    *bytes = weighted_ws(d, f);
+    return ok();
+}
+
+gsf_status gsf_filter3d_weighted(const void *in, const void *w, gsf_dtype t, gsf_dims d,
+                                 const gsf_filter *f, void *out, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    gsf_status st;
+    if ((st = check_dims(d)) || (st = check_filter(f)) || (st = check_ptr(in, 16, "in")) ||
+        (st = check_ptr(w, 16, "w")) || (st = check_ptr(out, 16, "out")) ||
+        (st = check_dtype(t, "t")))
+        return st;
+    if (t != GSF_F32)
+        return fail(GSF_ERR_UNSUPPORTED, "the weighted convolution is implemented for GSF_F32");
+    const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
+    const size_t need = weighted_ws(d, f);
+    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((st = check_ptr(ws, 16, "ws"))) return st;
+    if (overlaps(in, nb, out, nb) || overlaps(w, nb, out, nb) || overlaps(in, nb, ws, need) ||
+        overlaps(w, nb, ws, need) || overlaps(out, nb, ws, need))
+        return fail(GSF_ERR_INVALID_ARG, "in, w, out and ws must not overlap");
+    const gsf::Taps txy = make_taps(f->sigma_xy, f->truncate);
+    const gsf::Taps tz = make_taps(f->sigma_z, f->truncate);
+    const gsf::Dims dd = to_dims(d);
+    const gsf::Halo h = gsf::no_halo(dd);
+    const hipStream_t s = (hipStream_t)stream;
+    // [P = d*w][T1][D][generic-path scratch]; N goes to out
+    const size_t c = cube_bytes(d);
+    float *P = (float *)ws;
+    float *T1 = (float *)((char *)ws + c);
+    float *D = (float *)((char *)ws + 2 * c);
+    void *tmp = (char *)ws + 3 * c;
+    hipError_t e = gsf::launch_mul((const float *)in, (const float *)w, P, dd.voxels(), s);
+    if (e == hipSuccess) e = gsf::launch_zpass(P, T1, gsf::Store::F32, dd, h, tz, s);
+    if (e == hipSuccess)
+        e = gsf::launch_yx(T1, out, tmp, gsf::Store::F32, dd, h, txy, nullptr, nullptr, s);
+    if (e == hipSuccess) e = gsf::launch_zpass(w, T1, gsf::Store::F32, dd, h, tz, s);
+    if (e == hipSuccess)
+        e = gsf::launch_yx(T1, D, tmp, gsf::Store::F32, dd, h, txy, nullptr, nullptr, s);
+    if (e == hipSuccess) e = gsf::launch_div((const float *)out, D, (float *)out, dd.voxels(), s);
+    return device_status(e, "gsf_filter3d_weighted launch");
 }
 
 gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes)

@@ -110,6 +110,9 @@ hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double
 hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *shift, float *ws1,
                         float *ws2, float *ws3, float *ws4, float *mean, float *stdev,
                         uint64_t *mask, double k, hipStream_t s);
+// Weighted convolution pieces: P = d * w; F = N / D (0 where D == 0).
+hipError_t launch_mul(const float *d, const float *w, float *P, int64_t n, hipStream_t s);
+hipError_t launch_div(const float *N, const float *D, float *F, int64_t n, hipStream_t s);
 hipError_t launch_threshold(const void *F, Store st, const float *mean, const float *stdev,
                             Dims d, double k, uint64_t *mask, hipStream_t s);
 

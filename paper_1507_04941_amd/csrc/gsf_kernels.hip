@@ -6,6 +6,8 @@
 // sums of F - s and (F - s)^2.  Selection: F > mean + k*std.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gsf_device.h"
 #include "gsf_internal.h"
 
@@ -267,6 +269,32 @@ __global__ __launch_bounds__(kBlock) void k_threshold(const St *__restrict__ F,
     if ((threadIdx.x & 63) == 0 && z < nz) mask[row * W + z / 64] = word;
 }
 
+// ---------------------------------------------------------------------------
+// Weighted convolution (Eq. 1): elementwise product and quotient.
+// ---------------------------------------------------------------------------
+
+// P = d * w, grid-stride over the cube.
+__global__ __launch_bounds__(kBlock) void k_mul(const float *__restrict__ d,
+                                                const float *__restrict__ w,
+                                                float *__restrict__ P, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        P[i] = d[i] * w[i];
+}
+
+// F = N / D where D != 0, else 0 (no weighted support).  F may be N (in
+// place: each element is read, then written, by the same lane).
+__global__ __launch_bounds__(kBlock) void k_div(const float *N, const float *__restrict__ D,
+                                                float *F, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const float den = D[i];
+        F[i] = den != 0.0f ? N[i] / den : 0.0f;
+    }
+}
+
 inline unsigned ztiles(int64_t nz) { return (unsigned)((nz + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -367,6 +395,22 @@ hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *sh
         }
         return hipGetLastError();
     });
+}
+
+hipError_t launch_mul(const float *d, const float *w, float *P, int64_t n, hipStream_t s)
+{
+    prof::Scope scope_("k_mul", s);
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_mul, dim3((unsigned)blocks), dim3(kBlock), 0, s, d, w, P, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_div(const float *N, const float *D, float *F, int64_t n, hipStream_t s)
+{
+    prof::Scope scope_("k_div", s);
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_div, dim3((unsigned)blocks), dim3(kBlock), 0, s, N, D, F, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_threshold(const void *F, Store st, const float *mean, const float *stdev,
