@@ -89,8 +89,12 @@ __device__ __forceinline__ float zwin(double u, double v, double *q, int lane, i
     return (float)h;
 }
 
-constexpr int kAhead = 4;    // rows the y walk loads before use
-constexpr int kAheadX = 4;   // planes the x walk loads before use
+// Loads issued ahead of use.  The y walk is latency-bound: 16 rows ahead
+// (2 waves per SIMD) beat 4 rows (3 waves) and 32 (register-starved).  The
+// x walk's time does not move between 4 and 16 planes ahead, and 4 keeps it
+// at 3 waves per SIMD.
+constexpr int kAhead = 16;    // rows the y walk loads before use
+constexpr int kAheadX = 4;    // planes the x walk loads before use
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
@@ -101,7 +105,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
                                                      float *__restrict__ G1,
                                                      float *__restrict__ G2)
 {
-    static_assert(BY % kAhead == 0, "ring length must be a multiple of the prefetch depth");
+    constexpr int AH = BY < kAhead ? BY : kAhead;   // prefetch depth, at most the ring length
+    static_assert(BY % AH == 0, "ring length must be a multiple of the prefetch depth");
     __shared__ double qs[4][2][128];
     const int lane = threadIdx.x & 63;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -137,10 +142,10 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
     float ring0[BY], ring1[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ring0[j] = ring1[j] = 0.0f;
-    // rows kAhead steps ahead; rows past the cube and dead columns load 0
-    raw_t<St> pf0[kAhead], pf1[kAhead];
+    // rows AH steps ahead; rows past the cube and dead columns load 0
+    raw_t<St> pf0[AH], pf1[AH];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
+    for (int j = 0; j < AH; ++j) {
         pf0[j] = sbuf_ld_raw<St>(rf, o0 + (uint32_t)j * frow_b);
         pf1[j] = sbuf_ld_raw<St>(rf, o1 + (uint32_t)j * frow_b);
     }
@@ -157,11 +162,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
         for (int j = 0; j < BY; ++j) {
             const int64_t yin = y0 + j;                   // yin mod BY == j
             const bool row = yin < ny;
-            const float e0 = (row && v0) ? from_raw<St>(pf0[j % kAhead]) - s : 0.0f;
-            const float e1 = (row && v1) ? from_raw<St>(pf1[j % kAhead]) - s : 0.0f;
-            const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
-            pf0[j % kAhead] = sbuf_ld_raw<St>(rf, o0 + ra);
-            pf1[j % kAhead] = sbuf_ld_raw<St>(rf, o1 + ra);
+            const float e0 = (row && v0) ? from_raw<St>(pf0[j % AH]) - s : 0.0f;
+            const float e1 = (row && v1) ? from_raw<St>(pf1[j % AH]) - s : 0.0f;
+            const uint32_t ra = (uint32_t)(yin + AH) * frow_b;   // past ny: outside the plane
+            pf0[j % AH] = sbuf_ld_raw<St>(rf, o0 + ra);
+            pf1[j % AH] = sbuf_ld_raw<St>(rf, o1 + ra);
             const float l0 = ring0[j], l1 = ring1[j];
             ring0[j] = e0;
             ring1[j] = e1;
@@ -253,7 +258,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ 
                                                          float *__restrict__ G2)
 {
 #pragma clang fp contract(off)
-    static_assert(BY % kAhead == 0, "ring length must be a multiple of the prefetch depth");
+    constexpr int AH = BY < kAhead ? BY : kAhead;   // prefetch depth, at most the ring length
+    static_assert(BY % AH == 0, "ring length must be a multiple of the prefetch depth");
     static_assert(BZ == 16 || BZ == 32 || BZ == 64, "segment length");
     // a plane holds at most 2^28 voxels, so in-plane indices fit 32 bits
     const int ny = (int)ny64, nz = (int)nz64;
@@ -289,9 +295,9 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ 
     float ringa[BY], ringb[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ringa[j] = ringb[j] = 0.0f;
-    raw_t<St> pfa[kAhead], pfb[kAhead];
+    raw_t<St> pfa[AH], pfb[AH];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
+    for (int j = 0; j < AH; ++j) {
         pfa[j] = sbuf_ld_raw<St>(rf, oa + (uint32_t)j * frow_b);
         pfb[j] = sbuf_ld_raw<St>(rf, ob + (uint32_t)j * frow_b);
     }
@@ -303,11 +309,11 @@ __global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ 
         for (int j = 0; j < BY; ++j) {
             const int yin = y0 + j;                       // yin mod BY == j
             const bool row = yin < ny;
-            const float ea = (row && va) ? from_raw<St>(pfa[j % kAhead]) - s : 0.0f;
-            const float eb = (row && vb) ? from_raw<St>(pfb[j % kAhead]) - s : 0.0f;
-            const uint32_t ra = (uint32_t)(yin + kAhead) * frow_b;   // past ny: outside the plane
-            pfa[j % kAhead] = sbuf_ld_raw<St>(rf, oa + ra);
-            pfb[j % kAhead] = sbuf_ld_raw<St>(rf, ob + ra);
+            const float ea = (row && va) ? from_raw<St>(pfa[j % AH]) - s : 0.0f;
+            const float eb = (row && vb) ? from_raw<St>(pfb[j % AH]) - s : 0.0f;
+            const uint32_t ra = (uint32_t)(yin + AH) * frow_b;   // past ny: outside the plane
+            pfa[j % AH] = sbuf_ld_raw<St>(rf, oa + ra);
+            pfb[j % AH] = sbuf_ld_raw<St>(rf, ob + ra);
             const float la = ringa[j], lb = ringb[j];
             ringa[j] = ea;
             ringb[j] = eb;
@@ -383,14 +389,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const E *c, int p, 
 // 32-bit: every BX steps the kernel sets up descriptors over the next BX
 // planes of each stream and steps through them with scalar offsets, which
 // needs BX + 1 planes to span less than 2^31 bytes.
-template <int BX, typename St>
+template <int BX, typename St, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const float *__restrict__ G1, const float *__restrict__ G2, const St *__restrict__ F,
     int64_t nx64, int64_t ny64, int64_t nz64, int by, int bz, const double *__restrict__ shift,
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
 #pragma clang fp contract(off)
-    static_assert(BX % kAheadX == 0 && BX <= 64, "ring length");
+    constexpr int AX = BX < kAheadX ? BX : kAheadX;   // prefetch depth, at most the ring length
+    static_assert(BX % AX == 0 && BX <= 64, "ring length");
     const int nx = (int)nx64, ny = (int)ny64, nz = (int)nz64;
     const int y = blockIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -414,16 +421,16 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     float r1[BX], r2[BX];
 #pragma unroll
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
-    // loads issued kAheadX steps early: plane pa of G (entering) and plane
+    // loads issued AX steps early: plane pa of G (entering) and plane
     // pa - hix of F (output)
-    float pg1[kAheadX], pg2[kAheadX];
-    raw_t<St> pfv[kAheadX];
+    float pg1[AX], pg2[AX];
+    raw_t<St> pfv[AX];
     {
-        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, kAheadX, nx, plane);
-        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, kAheadX, nx, plane);
-        const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, kAheadX, nx, plane);
+        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, AX, nx, plane);
+        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, AX, nx, plane);
+        const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, AX, nx, plane);
 #pragma unroll
-        for (int j = 0; j < kAheadX; ++j) {
+        for (int j = 0; j < AX; ++j) {
             const int xf = j - hix;
             pg1[j] = buf_ld(q1, off + (uint32_t)j * plane_b);
             pg2[j] = buf_ld(q2, off + (uint32_t)j * plane_b);
@@ -439,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
         // planes loaded in this ring turn: G planes ga + j, F planes fa + j;
         // output planes xo + j (j < BX).  A plane offset of BX planes is
         // outside every span.
-        const int ga = p0 + kAheadX;
+        const int ga = p0 + AX;
         const int fa = ga - hix;
         const int fb = fa > 0 ? fa : 0;
         const int xo = p0 - hix;
@@ -451,13 +458,13 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
         const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane);
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
-            const float g1 = pg1[j % kAheadX], g2 = pg2[j % kAheadX];
-            const raw_t<St> fraw = pfv[j % kAheadX];
+            const float g1 = pg1[j % AX], g2 = pg2[j % AX];
+            const raw_t<St> fraw = pfv[j % AX];
             const int xf = fa + j;
             const uint32_t og = off + (uint32_t)j * pb;
-            pg1[j % kAheadX] = buf_ld(rg1, og);
-            pg2[j % kAheadX] = buf_ld(rg2, og);
-            pfv[j % kAheadX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
+            pg1[j % AX] = buf_ld(rg1, og);
+            pg2[j % AX] = buf_ld(rg2, og);
+            pfv[j % AX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
             s1 += (double)g1 - (double)r1[j];
             s2 += (double)g2 - (double)r2[j];
             r1[j] = g1;
@@ -476,8 +483,10 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
                 const float mf = (float)(s + m1);
                 const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
                 const uint32_t so = off + (uint32_t)(x - xb) * pb;
-                if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
-                if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
+                if (STATS) {   // compiled out when only masks are wanted
+                    if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
+                    if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
+                }
                 if (mrow) {
                     const float fv = from_raw<St>(fraw);
                     const bool bit = live && (double)fv > (double)mf + k * (double)sf;
@@ -557,8 +566,12 @@ hipError_t box_x_select(const float *G1, const float *G2, const void *F, Dims d,
 {
     const dim3 grid((unsigned)((d.nz + kThreads - 1) / kThreads), (unsigned)d.ny);
     prof::Scope scope(x_name<St>(BX), s);
-    hipLaunchKernelGGL((k_box_x_select<BX, St>), grid, dim3(kThreads), 0, s, G1, G2, (const St *)F,
-                       d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
+    if (mean || stdev)
+        hipLaunchKernelGGL((k_box_x_select<BX, St, true>), grid, dim3(kThreads), 0, s, G1, G2,
+                           (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
+    else
+        hipLaunchKernelGGL((k_box_x_select<BX, St, false>), grid, dim3(kThreads), 0, s, G1, G2,
+                           (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
     return hipGetLastError();
 }
 
