@@ -56,7 +56,7 @@ extern "C" {
 typedef enum gsf_status {
     GSF_OK = 0,
     GSF_ERR_INVALID_ARG = 1,  /* null/misaligned pointer, bad size, sigma, box, k, overlap */
-    GSF_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+    GSF_ERR_UNSUPPORTED = 2,  /* valid request the library does not implement */
     GSF_ERR_WORKSPACE = 3,    /* workspace smaller than the *_workspace_size figure */
     GSF_ERR_DEVICE = 4,       /* a HIP call or kernel launch failed */
     GSF_ERR_BUDGET = 5        /* request larger than an imposed memory budget */
