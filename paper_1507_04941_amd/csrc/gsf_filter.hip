@@ -385,9 +385,13 @@ const ZFn *ztab_of(std::integer_sequence<int, R...>)
 // 8 waves per block so a block's y tile (8 waves x P rows) is tall enough to
 // amortise the 2R halo rows it re-reads: blocks sweeping x drift apart, so
 // halo rows are not shared through L2 across blocks.  P shrinks as the ring
-// of 2R+1 partial sums per row grows (at most 256 VGPRs per lane).
+// of 2R+1 partial sums per row grows.
+// Rows per lane, measured on the 512x512x1024 cube.  R = 12: two rows (115
+// VGPRs, two 8-wave blocks per CU) 0.70 ms, three rows (one block per CU)
+// 0.89 ms, one row (3.5x halo rows per output row) 0.87 ms.  R = 6: two rows
+// 0.49 ms, three 0.52 ms, four 0.51 ms.  R = 3: four rows 0.43 ms.
 template <int R>
-constexpr int yx_rows() { return R <= 6 ? 4 : R <= 12 ? 3 : 1; }
+constexpr int yx_rows() { return R <= 3 ? 4 : R <= 12 ? 2 : 1; }
 
 template <typename St, int... R>
 const YXFn *yxtab_of(std::integer_sequence<int, R...>)
