@@ -388,7 +388,9 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
 // streams forked from the caller's stream, each with its own workspace slot
 // [T1][F scratch][statistics workspace]; a single cube runs on the caller's
 // stream.
-constexpr int kSlots = 4;
+// Measured on the 96-sub-cube batch: 4 slots 85 ms per call, 8 slots 78 ms,
+// 16 slots 75 ms (each slot holds a workspace for the largest cube).
+constexpr int kSlots = 16;
 
 int find_slots(int32_t ncubes) { return ncubes < kSlots ? ncubes : kSlots; }
 
