@@ -13,7 +13,7 @@
 //     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of
 //     y, and sweeps an x range plane by plane.  The block's waves load each
 //     plane's NW*P + 2R rows once, cooperatively, two planes ahead, into a
-//     three-stage LDS ring (one barrier per plane); each lane then forms the
+//     two-stage LDS ring (one barrier per plane); each lane then forms the
 //     y pass of its P points from LDS and scatters it into a register ring of
 //     2R+1 partial x sums per point; the oldest sum is complete and written
 //     after every plane.  T1 is read once (plus the 2R halo rows per block)
@@ -189,7 +189,12 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     constexpr int TY = NW * P;            // output rows of the block
     constexpr int TR = TY + 2 * R;        // rows of T1 one plane of the block needs
     constexpr int LW = (TR + NW - 1) / NW;   // rows each wave loads per plane
-    constexpr int S = 3;                  // LDS stages: read xp, written xp+1, retired xp-1
+    // One barrier every PB planes, 2 PB LDS stages (PB being read, PB being
+    // written).  Measured with R = 12: one barrier per plane and two stages
+    // 0.665 ms, one per two planes and four stages 0.668 ms; storing the next
+    // plane before the barrier instead (three stages) 0.695 ms.
+    constexpr int PB = 1;
+    constexpr int S = 2 * PB;
     __shared__ float stage[S][TR][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -244,15 +249,20 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             if (tr < TR) stage[st][tr][lane] = from_raw<St>(r[i]);
         }
     };
-    // prologue: plane base in LDS, planes base+1 and base+2 in registers.
-    // Each step writes plane xp+1 to its stage and issues the loads of plane
-    // xp+3, so a load has two planes of compute to arrive.
+    // prologue: planes base .. base+PB-1 in LDS, planes base+PB and
+    // base+PB+1 in registers.  Every PB planes a barrier makes the next PB
+    // stored planes visible and retires the PB planes read before it; step xp
+    // stores plane xp+PB (into the stage of retired plane xp-PB) and issues
+    // the loads of plane xp+PB+2, so a load has two planes of compute to
+    // arrive.
     raw_t<St> ra[LW], rb[LW];
-    load_plane(base, ra);
-    store_stage(base % S < 0 ? base % S + S : base % S, ra);
-    load_plane(base + 1, ra);
-    load_plane(base + 2, rb);
-    int64_t sx = ((base % S) + S) % S;                      // stage holding plane xp
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+        load_plane(base + k, ra);
+        store_stage((int)((base + k) & (S - 1)), ra);
+    }
+    load_plane(base + PB, ra);
+    load_plane(base + PB + 1, rb);
 
 #pragma nounroll
     for (int64_t p0 = base; p0 <= p_end; p0 += L) {
@@ -261,12 +271,12 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             // Every step of the rounded range runs: planes outside [0, nx)
             // read 0 and feed only outputs that are never written.
             const int64_t xp = p0 + j;                       // xp mod L == j
-            const int s1 = (int)(sx + 1 >= S ? sx + 1 - S : sx + 1);
-            store_stage(s1, ra);                             // plane xp+1
+            if (PB == 1 || ((xp - base) & (PB - 1)) == 0) __syncthreads();
+            store_stage((int)((xp + PB) & (S - 1)), ra);      // plane xp+PB
 #pragma unroll
-            for (int i = 0; i < LW; ++i) ra[i] = rb[i];      // plane xp+2 moves up
-            load_plane(xp + 3, rb);                          // plane xp+3
-            __syncthreads();                                 // plane xp complete; plane xp-1 retired
+            for (int i = 0; i < LW; ++i) ra[i] = rb[i];      // plane xp+PB+1 moves up
+            load_plane(xp + PB + 2, rb);                     // plane xp+PB+2
+            const int sx = (int)(xp & (S - 1));              // stage of plane xp
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 float t2 = 0.0f;
@@ -292,7 +302,6 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             }
 #pragma unroll
             for (int q = 0; q < P; ++q) acc[q][slot_o] = 0.0f;
-            sx = s1;
             __builtin_amdgcn_sched_barrier(0);
         }
     }
