@@ -2,11 +2,12 @@
 //
 // The window sums of a = F - s and a^2 over the box around each voxel are
 // computed as directional sums in two kernels:
-//   k_box_yz_seg<BY,BZ> (z window BZ = 16, 32, 64) and k_box_yz<BY> (any
-//     z window up to 65): for one x-plane and a 64-wide z strip per wave,
-//     walk y with a running window sum per column (the value leaving the
-//     window comes from a register ring of the last BY rows, so F is read
-//     once), then take the z window across lanes with DPP lane scans.
+//   k_box_yz_seg<BY,BZ,NW> (z window BZ = 16, 32, 64) and k_box_yz<BY> (any
+//     z window up to 65): for one x-plane, walk y with a running window sum
+//     per column (the value leaving the window comes from a register ring of
+//     the last BY rows, so F is read once), then take the z window across the
+//     lanes of a 64-wide strip with DPP lane scans (k_box_yz_seg: the column
+//     sums pass through an LDS tile shared by the block's NW waves).
 //     Writes the yz-window sums G1 = sum a, G2 = sum a^2 for every voxel.
 //   k_box_x_select<BX>: one lane per (y, z) walks x with a running window sum
 //     of G1, G2 (leaving plane from a register ring of the last BX planes),
@@ -237,101 +238,138 @@ __device__ __forceinline__ void seg_scan4(float (&v)[4])
     if constexpr (BZ >= 64) bcast31_level(v);
 }
 
+// Workgroups go to the 8 XCDs round robin (workgroup i to XCD i mod 8).
+// Renumbered, each XCD runs a contiguous range of logical blocks, so
+// neighbouring blocks share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t n)
+{
+    const int64_t q = n / 8, r = n % 8, xcd = i % 8, k = i / 8;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+}
+
+// Rows per LDS exchange of the segmented kernel.
+constexpr int kYzRows = 8;
+
 // The same job as k_box_yz for a power-of-two z window BZ, with the z window
-// built from sums that never subtract: the strip's columns are cut into
-// segments of BZ, and the window of output z is the tail of one segment plus
-// the head of the next.  Lane i (segment j = i / BZ, position q = i % BZ)
-// carries column A = start of segment j + BZ-1-q and column B = start of
-// segment j+1 + q.  After the y walk, an inclusive scan of the A values
-// inside each BZ-lane group gives at lane i the tail of segment j from
-// BZ-1-q, and a scan of the B values gives heads of segment j+1; lane i
-// therefore finishes output column j*BZ + BZ-1-q, adding the head of length
-// BZ-1-q fetched from lane j*BZ + BZ-2-q.  Column sums along y are FP64
-// running sums of FP32 increments, rounded once to FP32 before the scans; a
-// scan only adds same-window partial sums, so each window sum is accurate
-// relative to itself.
-template <int BY, int BZ, typename St>
-__global__ __launch_bounds__(kThreads) void k_box_yz_seg(const St *__restrict__ F, int64_t nx,
-                                                         int64_t ny64, int64_t nz64,
-                                                         const double *__restrict__ shift,
-                                                         float *__restrict__ G1,
-                                                         float *__restrict__ G2)
+// built from sums that never subtract.  Columns are cut into segments of BZ,
+// and the window of output z is the tail of one segment plus the head of the
+// next.
+//
+// A block owns one x-plane and NO = 64 (NW - 1) consecutive output columns.
+// Its NW waves walk y over the NO + 64 columns starting 32 before the first
+// output, one column per lane: FP64 running sums of the FP32 increments
+// (F - s) and (F - s)^2, the leaving row's value from a register ring of the
+// last BY rows.  Every kYzRows rows each lane writes its column's sums,
+// rounded once to FP32, to a double-buffered LDS tile and the block meets
+// at a barrier.  Then each of the first NW - 1 waves finishes the rows for
+// its 64-column strip: lane i (segment j = i / BZ, position q = i % BZ)
+// takes column A = start of segment j + BZ-1-q and column B = start of
+// segment j+1 + q from the tile; an inclusive scan of the A values inside
+// each BZ-lane group gives at lane i the tail of segment j from BZ-1-q, a
+// scan of the B values gives heads of segment j+1, and lane i finishes output
+// column j*BZ + BZ-1-q by adding the head of length BZ-1-q fetched from lane
+// j*BZ + BZ-2-q.  A scan only adds same-window partial sums, so each window
+// sum is accurate relative to itself.  Every column is walked once, plus one
+// strip of halo per block.
+//
+// Measured on the 512x512x1024 cube (64^3 box): 9 waves (one block per CU)
+// 0.63 ms; 5 waves (a quarter of the walk is halo) 0.70 ms; 16 rows per
+// exchange (the tile halves occupancy) 0.92 ms; 8 or 4 rows loaded ahead
+// instead of 16, 0.68 and 0.87 ms.  The earlier form, in which each lane
+// walked both its A and its B column (two rings, no LDS), took 0.65 ms.
+template <int BY, int BZ, int NW, typename St>
+__global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F, int64_t nx,
+                                                        int64_t ny64, int64_t nz64,
+                                                        const double *__restrict__ shift,
+                                                        float *__restrict__ G1,
+                                                        float *__restrict__ G2)
 {
 #pragma clang fp contract(off)
     constexpr int AH = BY < kAhead ? BY : kAhead;   // prefetch depth, at most the ring length
-    static_assert(BY % AH == 0, "ring length must be a multiple of the prefetch depth");
+    constexpr int YB = kYzRows < BY ? kYzRows : BY;
+    constexpr int NC = 64 * NW;                     // columns the block walks
+    constexpr int NO = NC - 64;                     // output columns of the block
+    static_assert(BY % AH == 0 && BY % YB == 0, "ring length");
     static_assert(BZ == 16 || BZ == 32 || BZ == 64, "segment length");
+    __shared__ float2 hs[2][YB][NC];
     // a plane holds at most 2^28 voxels, so in-plane indices fit 32 bits
     const int ny = (int)ny64, nz = (int)nz64;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nstrips = (nz + 63) / 64;
-    const int64_t job = (int64_t)blockIdx.x * 4 + wave;
-    if (job >= nx * nstrips) return;                 // whole wave exits together
-    const int64_t x = job / nstrips;
-    const int z0 = (int)(job % nstrips) * 64;
-    const int hiy = -(BY / 2) + BY - 1;
+    const int zblocks = (nz + NO - 1) / NO;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t x = blk / zblocks;
+    const int Z0 = (int)(blk % zblocks) * NO;
+    const int hiy = BY / 2 - 1;
     const float s = (float)shift[0];
     constexpr uint32_t SZ = sizeof(St);
     const int64_t plane = (int64_t)ny * nz;
     const uint32_t plane_b = (uint32_t)(plane * 4);     // G planes and rows (FP32)
     const uint32_t row_b = (uint32_t)nz * 4u;
     const uint32_t frow_b = (uint32_t)nz * SZ;          // F rows (storage type)
-    const int seg = lane / BZ, q = lane % BZ;
-    const int za = z0 - BZ / 2 + seg * BZ + (BZ - 1 - q);
-    const int zb = z0 - BZ / 2 + (seg + 1) * BZ + q;
-    const bool va = za >= 0 && za < nz;
-    const bool vb = zb >= 0 && zb < nz;
-    const uint32_t oa = va ? (uint32_t)za * SZ : kOOB;
-    const uint32_t ob = vb ? (uint32_t)zb * SZ : kOOB;
+    // the column this lane walks: tile column threadIdx.x
+    const int zc = Z0 - 32 + (int)threadIdx.x;
+    const uint32_t oc = zc >= 0 && zc < nz ? (uint32_t)zc * SZ : kOOB;
     const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, (uint32_t)(plane * SZ));
-    // output column of this lane and the lane holding the head it adds
-    const int zo = z0 + seg * BZ + (BZ - 1 - q);
-    const uint32_t og = zo < nz ? (uint32_t)zo * 4u : kOOB;
+    // output strip of wave w < NW - 1: columns Z0 + 64 w + 0..63; tile
+    // columns of its A and B values
+    const bool out_wave = wave < NW - 1;
+    const int seg = lane / BZ, q = lane % BZ;
+    const int ia = 64 * wave + 32 - BZ / 2 + seg * BZ + (BZ - 1 - q);
+    const int ib = ia + 2 * q + 1;
+    const int zo = Z0 + 64 * wave + seg * BZ + (BZ - 1 - q);
+    const uint32_t og = out_wave && zo < nz ? (uint32_t)zo * 4u : kOOB;
     const bool has_head = q < BZ - 1;
     const int src = has_head ? seg * BZ + (BZ - 2 - q) : lane;
     const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
     const __amdgpu_buffer_rsrc_t rg2 = buf(G2 + x * plane, plane_b);
-    float ringa[BY], ringb[BY];
+    float ring[BY];
 #pragma unroll
-    for (int j = 0; j < BY; ++j) ringa[j] = ringb[j] = 0.0f;
-    raw_t<St> pfa[AH], pfb[AH];
+    for (int j = 0; j < BY; ++j) ring[j] = 0.0f;
+    raw_t<St> pf[AH];
 #pragma unroll
-    for (int j = 0; j < AH; ++j) {
-        pfa[j] = sbuf_ld_raw<St>(rf, oa + (uint32_t)j * frow_b);
-        pfb[j] = sbuf_ld_raw<St>(rf, ob + (uint32_t)j * frow_b);
-    }
-    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;   // running y sums of columns A and B
+    for (int j = 0; j < AH; ++j) pf[j] = sbuf_ld_raw<St>(rf, oc + (uint32_t)j * frow_b);
+    double c1 = 0.0, c2 = 0.0;                      // running y sums of the column
     const int nsteps = ny + hiy;
+    int bsel = 0;                                   // tile buffer of the current rows
 #pragma nounroll
     for (int y0 = 0; y0 < nsteps; y0 += BY) {
 #pragma clang loop unroll(full)
         for (int j = 0; j < BY; ++j) {
             const int yin = y0 + j;                       // yin mod BY == j
-            const bool row = yin < ny;
-            const float ea = (row && va) ? from_raw<St>(pfa[j % AH]) - s : 0.0f;
-            const float eb = (row && vb) ? from_raw<St>(pfb[j % AH]) - s : 0.0f;
-            const uint32_t ra = (uint32_t)(yin + AH) * frow_b;   // past ny: outside the plane
-            pfa[j % AH] = sbuf_ld_raw<St>(rf, oa + ra);
-            pfb[j % AH] = sbuf_ld_raw<St>(rf, ob + ra);
-            const float la = ringa[j], lb = ringb[j];
-            ringa[j] = ea;
-            ringb[j] = eb;
-            a1 += (double)(ea - la);
-            a2 += (double)(ea * ea - la * la);
-            b1 += (double)(eb - lb);
-            b2 += (double)(eb * eb - lb * lb);
-            const int y = yin - hiy;
-            if (y >= 0 && y < ny) {
-                float t[4] = {(float)a1, (float)a2, (float)b1, (float)b2};
-                seg_scan4<BZ>(t);
-                const float h1 = __int_as_float(
-                    __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
-                const float h2 = __int_as_float(
-                    __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
-                const uint32_t oy = og + (uint32_t)y * row_b;
-                buf_st(rg1, has_head ? t[0] + h1 : t[0], oy);
-                buf_st(rg2, has_head ? t[1] + h2 : t[1], oy);
+            // rows past ny and columns outside [0, nz) count as 0 (their
+            // loads read 0 through the range check)
+            const float e = from_raw<St>(pf[j % AH]) - s;
+            const float ev = yin < ny && oc != kOOB ? e : 0.0f;
+            pf[j % AH] = sbuf_ld_raw<St>(rf, oc + (uint32_t)(yin + AH) * frow_b);
+            const float l = ring[j];
+            ring[j] = ev;
+            c1 += (double)(ev - l);
+            c2 += (double)(ev * ev - l * l);
+            hs[bsel][j % YB][threadIdx.x] = make_float2((float)c1, (float)c2);
+            if (j % YB == YB - 1) {
+                // rows yin-YB+1 .. yin are in the tile; the other buffer was
+                // last read before this barrier's predecessor
+                __syncthreads();
+                if (out_wave) {
+#pragma unroll
+                    for (int r = 0; r < YB; ++r) {
+                        const int y = yin - (YB - 1) + r - hiy;
+                        if (y >= 0 && y < ny) {
+                            const float2 a = hs[bsel][r][ia], b = hs[bsel][r][ib];
+                            float t[4] = {a.x, a.y, b.x, b.y};
+                            seg_scan4<BZ>(t);
+                            const float h1 = __int_as_float(
+                                __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
+                            const float h2 = __int_as_float(
+                                __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
+                            const uint32_t oy = og + (uint32_t)y * row_b;
+                            buf_st(rg1, has_head ? t[0] + h1 : t[0], oy);
+                            buf_st(rg2, has_head ? t[1] + h2 : t[1], oy);
+                        }
+                    }
+                }
+                bsel ^= 1;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -531,31 +569,47 @@ const char *x_name(int bx)
     return tab[bx == 8 ? 0 : bx == 16 ? 1 : bx == 32 ? 2 : 3].c_str();
 }
 
+template <int BY, int NW, typename St>
+hipError_t yz_seg(const St *F, Dims d, int bz, const double *shift, float *G1, float *G2,
+                  hipStream_t s)
+{
+    constexpr int NO = 64 * (NW - 1);
+    const dim3 grid((unsigned)(d.nx * ((d.nz + NO - 1) / NO)));
+    const dim3 block(64 * NW);
+    if (bz == 16)
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 16, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
+                           shift, G1, G2);
+    else if (bz == 32)
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 32, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
+                           shift, G1, G2);
+    else
+        hipLaunchKernelGGL((k_box_yz_seg<BY, 64, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
+                           shift, G1, G2);
+    return hipGetLastError();
+}
+
 template <int BY, typename St>
 hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G1, float *G2,
                   hipStream_t s)
 {
     const St *F = (const St *)F_;
-    const int64_t jobs = d.nx * ((d.nz + 63) / 64);
-    const dim3 grid((unsigned)((jobs + 3) / 4));
     prof::Scope scope(yz_name<St>(BY, bz), s);
-    switch (bz) {
-    case 16:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 16, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
-                           d.nz, shift, G1, G2);
-        break;
-    case 32:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 32, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
-                           d.nz, shift, G1, G2);
-        break;
-    case 64:
-        hipLaunchKernelGGL((k_box_yz_seg<BY, 64, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny,
-                           d.nz, shift, G1, G2);
-        break;
-    default:
-        hipLaunchKernelGGL((k_box_yz<BY, St>), grid, dim3(kThreads), 0, s, F, d.nx, d.ny, d.nz, bz,
-                           shift, G1, G2);
+    if (bz == 16 || bz == 32 || bz == 64) {
+        // 3, 5 or 9 waves per block (2, 4 or 8 output strips), whichever
+        // walks the fewest columns for this depth (ties to the larger block)
+        int best = 9;
+        int64_t cost = 0;
+        for (int nw : {9, 5, 3}) {
+            const int64_t c = (d.nz + 64 * (nw - 1) - 1) / (64 * (nw - 1)) * nw;
+            if (nw == 9 || c < cost) best = nw, cost = c;
+        }
+        if (best == 3) return yz_seg<BY, 3, St>(F, d, bz, shift, G1, G2, s);
+        if (best == 5) return yz_seg<BY, 5, St>(F, d, bz, shift, G1, G2, s);
+        return yz_seg<BY, 9, St>(F, d, bz, shift, G1, G2, s);
     }
+    const int64_t jobs = d.nx * ((d.nz + 63) / 64);
+    hipLaunchKernelGGL((k_box_yz<BY, St>), dim3((unsigned)((jobs + 3) / 4)), dim3(kThreads), 0, s,
+                       F, d.nx, d.ny, d.nz, bz, shift, G1, G2);
     return hipGetLastError();
 }
 
