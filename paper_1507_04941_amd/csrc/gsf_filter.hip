@@ -12,8 +12,8 @@
 //   k_yx_r<R, P, NW>: F = gxy * (gxy * T1 along y) along x.  A block owns a
 //     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of
 //     y, and sweeps an x range plane by plane.  The block's waves load each
-//     plane's NW*P + 2R rows once, cooperatively, two planes ahead, into a
-//     two-stage LDS ring (one barrier per plane); each lane then forms the
+//     plane's NW*P + 2R rows once, cooperatively, two or three planes ahead,
+//     into a two-stage LDS ring (one barrier per plane); each lane then forms the
 //     y pass of its P points from LDS and scatters it into a register ring of
 //     2R+1 partial x sums per point; the oldest sum is complete and written
 //     after every plane.  T1 is read once (plus the 2R halo rows per block)
@@ -189,12 +189,16 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     constexpr int TY = NW * P;            // output rows of the block
     constexpr int TR = TY + 2 * R;        // rows of T1 one plane of the block needs
     constexpr int LW = (TR + NW - 1) / NW;   // rows each wave loads per plane
-    // One barrier every PB planes, 2 PB LDS stages (PB being read, PB being
-    // written).  Measured with R = 12: one barrier per plane and two stages
-    // 0.665 ms, one per two planes and four stages 0.668 ms; storing the next
-    // plane before the barrier instead (three stages) 0.695 ms.
-    constexpr int PB = 1;
-    constexpr int S = 2 * PB;
+    // Two LDS stages, one barrier per plane: plane xp is read from one stage
+    // while plane xp+1 is stored into the other, after the barrier that
+    // retired plane xp-1.  Measured with R = 12: 0.665 ms; one barrier per two
+    // planes with four stages 0.668 ms; storing the next plane before the
+    // barrier (three stages) 0.695 ms.
+    constexpr int S = 2;
+    // Planes held in registers ahead of their store.  Measured: R = 12, 6, 3
+    // with two planes 0.666, 0.477, 0.436 ms; three 0.645, 0.464, 0.441 ms;
+    // four 0.795 ms for R = 12 (its registers then allow one block per CU).
+    constexpr int D = R <= 3 ? 2 : 3;
     __shared__ float stage[S][TR][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -249,20 +253,15 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             if (tr < TR) stage[st][tr][lane] = from_raw<St>(r[i]);
         }
     };
-    // prologue: planes base .. base+PB-1 in LDS, planes base+PB and
-    // base+PB+1 in registers.  Every PB planes a barrier makes the next PB
-    // stored planes visible and retires the PB planes read before it; step xp
-    // stores plane xp+PB (into the stage of retired plane xp-PB) and issues
-    // the loads of plane xp+PB+2, so a load has two planes of compute to
-    // arrive.
-    raw_t<St> ra[LW], rb[LW];
+    // prologue: plane base in LDS, planes base+1 .. base+D in registers.
+    // Step xp meets the barrier (plane xp visible, plane xp-1 retired),
+    // stores plane xp+1 into the retired stage and issues the loads of plane
+    // xp+D+1, so a load has D planes of compute to arrive.
+    raw_t<St> rq[D][LW];
+    load_plane(base, rq[0]);
+    store_stage((int)(base & (S - 1)), rq[0]);
 #pragma unroll
-    for (int k = 0; k < PB; ++k) {
-        load_plane(base + k, ra);
-        store_stage((int)((base + k) & (S - 1)), ra);
-    }
-    load_plane(base + PB, ra);
-    load_plane(base + PB + 1, rb);
+    for (int k = 0; k < D; ++k) load_plane(base + 1 + k, rq[k]);
 
 #pragma nounroll
     for (int64_t p0 = base; p0 <= p_end; p0 += L) {
@@ -271,11 +270,13 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             // Every step of the rounded range runs: planes outside [0, nx)
             // read 0 and feed only outputs that are never written.
             const int64_t xp = p0 + j;                       // xp mod L == j
-            if (PB == 1 || ((xp - base) & (PB - 1)) == 0) __syncthreads();
-            store_stage((int)((xp + PB) & (S - 1)), ra);      // plane xp+PB
+            __syncthreads();
+            store_stage((int)((xp + 1) & (S - 1)), rq[0]);   // plane xp+1
 #pragma unroll
-            for (int i = 0; i < LW; ++i) ra[i] = rb[i];      // plane xp+PB+1 moves up
-            load_plane(xp + PB + 2, rb);                     // plane xp+PB+2
+            for (int k = 0; k + 1 < D; ++k)
+#pragma unroll
+                for (int i = 0; i < LW; ++i) rq[k][i] = rq[k + 1][i];
+            load_plane(xp + D + 1, rq[D - 1]);               // plane xp+D+1
             const int sx = (int)(xp & (S - 1));              // stage of plane xp
 #pragma unroll
             for (int q = 0; q < P; ++q) {
