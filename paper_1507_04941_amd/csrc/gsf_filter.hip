@@ -2,13 +2,12 @@
 //
 // The 3-D filter is the outer product gxy (x) gxy (x) gz, so Eq. 2 is applied
 // as a spectral pass followed by a fused spatial pass:
-//   k_zpass_r<R>: T1 = gz * d along z (contiguous).  A block stages one row
-//     segment with its +-R halo in LDS using coalesced loads; every lane then
-//     holds a (4 + 2R)-wide window in registers (ds_read_b128) and produces 4
-//     consecutive outputs, so each staged value feeds up to 4(2R+1) FMAs.
-//   k_zpass_rows<R>: the same for rows of a multiple of 4 values, with a
-//     block walking 16 rows, 16-byte row loads one row ahead of use and a
-//     double-buffered tile.
+//   k_zpass_rows<R>: T1 = gz * d along z (contiguous).  A block walks 16
+//     rows of a 1024-wide z chunk, staging each row with its +-R halo in a
+//     double-buffered LDS tile one row ahead of use (coalesced loads); every
+//     lane then holds a (4 + 2R)-wide window in registers (ds_read_b128) and
+//     produces 4 consecutive outputs, so each staged value feeds up to
+//     4(2R+1) FMAs.
 //   k_yx_r<R, P, NW>: F = gxy * (gxy * T1 along y) along x.  A block owns a
 //     64-wide z strip (one lane per z, coalesced rows) and NW waves x P rows of
 //     y, and sweeps an x range plane by plane.  The block's waves load each
@@ -64,58 +63,16 @@ __device__ __forceinline__ void store4(St *p, const float (&v)[4])
     }
 }
 
-template <int R, typename St>
-__global__ __launch_bounds__(kThreads) void k_zpass_r(const St *__restrict__ in,
-                                                      St *__restrict__ out, int64_t nz,
-                                                      int64_t NZ, int64_t zoff, Taps t)
-{
-    constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
-    __shared__ float4 tile4[kZOut / 4 + NW + 1];
-    float *tile = reinterpret_cast<float *>(tile4);
-    const int64_t row = blockIdx.x;
-    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
-    // output z (core) reads input z + zoff of a row of NZ values
-    const St *src = in + row * NZ + zoff;
-    for (int i = threadIdx.x; i < 4 * (kZOut / 4 + NW + 1); i += kThreads) {
-        const int64_t z = z0 - R + i;
-        tile[i] = (z + zoff >= 0 && z + zoff < NZ) ? widen(src[z]) : 0.0f;
-    }
-    __syncthreads();
-    float w[4 * NW];
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-        const float4 q = tile4[threadIdx.x + j];
-        w[4 * j] = q.x;
-        w[4 * j + 1] = q.y;
-        w[4 * j + 2] = q.z;
-        w[4 * j + 3] = q.w;
-    }
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int o = 0; o <= 2 * R; ++o) {
-        const float g = t.g[o];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
-    }
-    const int64_t z = z0 + 4 * threadIdx.x;
-    St *dst = out + row * nz + z;
-    if (sizeof(St) == 4 && z + 3 < nz && (((uintptr_t)dst) & 15) == 0) {
-        store4(dst, acc);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (z + k < nz) dst[k] = narrow<St>(acc[k]);
-    }
-}
-
-// The same spectral pass for rows whose length is a multiple of 4 (so every
-// row starts aligned for 4-element loads): a block walks kZRows consecutive
-// rows of one 1024-wide z chunk, loading each row with 4-element loads one
-// row ahead of its use into a double-buffered FP32 LDS tile (one barrier per
-// row).
+// The spectral pass: a block walks kZRows consecutive rows of one 1024-wide
+// z chunk (four outputs per lane), loading each row one row ahead of its use
+// into a double-buffered FP32 LDS tile (one barrier per row).  When the row
+// lengths and the z halo are multiples of 4 (A), every row starts aligned
+// and a lane loads and stores its four values with single 4-element
+// accesses; otherwise it uses element accesses through range-checked buffer
+// descriptors (values past the row read 0, stores past it are dropped).
 constexpr int kZRows = 16;
 
-template <int R, typename St>
+template <int R, typename St, bool A>
 __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
                                                          St *__restrict__ out, int64_t nrows,
                                                          int64_t nz, int64_t NZ, int64_t zoff,
@@ -123,27 +80,42 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
     constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
+    constexpr uint32_t SZ = sizeof(St);
     __shared__ float4 tile4[2][TL / 4];
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * kZRows;
     const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
     const int64_t z0 = (int64_t)blockIdx.y * kZOut;
-    // core z of the output maps to input z + zoff in rows of NZ values; all
-    // of nz, NZ and zoff are multiples of 4, so four values are all in or out
+    // core z of the output maps to input z + zoff in rows of NZ values
     const int64_t zm = z0 + 4 * tid;                 // this lane's four values and outputs
-    const bool mine = zm < nz;                       // outputs inside the core
-    const bool load = zm + zoff < NZ;                // inputs inside the array
+    const bool mine = zm < nz;                       // outputs inside the core (A)
+    const bool load = zm + zoff < NZ;                // inputs inside the array (A)
     // halo: lanes 0 .. 2R-1 fetch z0 - R + lane (left) and z0 + kZOut + lane - R (right)
     const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
     const bool halo = tid < 2 * R && zh + zoff >= 0 && zh + zoff < NZ;
     const int th = tid < R ? tid : kZOut + tid;      // its tile index
-    float4 m = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float h = 0.0f;
-    {
-        const St *row = in + r0 * NZ + zoff;
-        if (load) m = load4(row + zm);
-        if (halo) h = widen(row[zh]);
-    }
+    // element form: byte offsets inside a row (zm + zoff >= 0; a row is
+    // below 2^31 bytes)
+    const uint32_t om = (uint32_t)((zm + zoff) * SZ);
+    const uint32_t oh = halo ? (uint32_t)((zh + zoff) * SZ) : kOOB;
+    const uint32_t os = (uint32_t)(zm * SZ);
+    auto fetch = [&](int64_t r, float4 &m, float &h) {
+        if constexpr (A) {
+            const St *row = in + r * NZ + zoff;
+            m = load ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
+            h = halo ? widen(row[zh]) : 0.0f;
+        } else {
+            const __amdgpu_buffer_rsrc_t rr = buf(in + r * NZ, (uint32_t)(NZ * SZ));
+            m.x = sbuf_ld<St>(rr, om);
+            m.y = sbuf_ld<St>(rr, om + SZ);
+            m.z = sbuf_ld<St>(rr, om + 2 * SZ);
+            m.w = sbuf_ld<St>(rr, om + 3 * SZ);
+            h = sbuf_ld<St>(rr, oh);
+        }
+    };
+    float4 m;
+    float h;
+    fetch(r0, m, h);
     for (int64_t r = r0; r < r1; ++r) {
         const int b = (int)((r - r0) & 1);
         float *tile = reinterpret_cast<float *>(tile4[b]);
@@ -153,11 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
         tile[R + 4 * tid + 3] = m.w;
         if (tid < 2 * R) tile[th] = h;
         __syncthreads();
-        if (r + 1 < r1) {
-            const St *row = in + (r + 1) * NZ + zoff;
-            m = load ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
-            h = halo ? widen(row[zh]) : 0.0f;
-        }
+        if (r + 1 < r1) fetch(r + 1, m, h);
         float w[4 * NW];
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
@@ -174,7 +142,13 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
         }
-        if (mine) store4(out + r * nz + zm, acc);
+        if constexpr (A) {
+            if (mine) store4(out + r * nz + zm, acc);
+        } else {
+            const __amdgpu_buffer_rsrc_t ro = buf(out + r * nz, (uint32_t)(nz * SZ));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sbuf_st<St>(ro, acc[k], os + (uint32_t)k * SZ);
+        }
     }
 }
 
@@ -235,7 +209,6 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     double fsum = 0.0;                                       // this lane's share of sum(F)
     const int64_t p_start = xa - R;
     const int64_t p_end = xb - 1 + R;                       // inclusive
-    int64_t base = p_start >= 0 ? (p_start / L) * L : -(((-p_start) + L - 1) / L) * L;
 
     // a plane outside [0, nx) gets an empty range, so its rows read 0
     // loads stay raw until stored to LDS two planes later
@@ -253,23 +226,26 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
             if (tr < TR) stage[st][tr][lane] = from_raw<St>(r[i]);
         }
     };
-    // prologue: plane base in LDS, planes base+1 .. base+D in registers.
-    // Step xp meets the barrier (plane xp visible, plane xp-1 retired),
-    // stores plane xp+1 into the retired stage and issues the loads of plane
-    // xp+D+1, so a load has D planes of compute to arrive.
+    // prologue: plane p_start in LDS, planes p_start+1 .. p_start+D in
+    // registers.  Step xp meets the barrier (plane xp visible, plane xp-1
+    // retired), stores plane xp+1 into the retired stage and issues the loads
+    // of plane xp+D+1, so a load has D planes of compute to arrive.  Ring
+    // turns start at p_start (the ring slot of plane xp is (xp - p_start)
+    // mod L) and the last turn runs to its end: the surplus planes read 0 or
+    // feed only outputs past xb, which are never written.  (Branching around
+    // them defeats the load pipelining.)
     raw_t<St> rq[D][LW];
-    load_plane(base, rq[0]);
-    store_stage((int)(base & (S - 1)), rq[0]);
+    load_plane(p_start, rq[0]);
+    store_stage((int)(p_start & (S - 1)), rq[0]);
 #pragma unroll
-    for (int k = 0; k < D; ++k) load_plane(base + 1 + k, rq[k]);
+    for (int k = 0; k < D; ++k) load_plane(p_start + 1 + k, rq[k]);
 
 #pragma nounroll
-    for (int64_t p0 = base; p0 <= p_end; p0 += L) {
+    for (int64_t p0 = p_start; p0 <= p_end; p0 += L) {
 #pragma unroll
         for (int j = 0; j < L; ++j) {
-            // Every step of the rounded range runs: planes outside [0, nx)
-            // read 0 and feed only outputs that are never written.
-            const int64_t xp = p0 + j;                       // xp mod L == j
+            // Planes outside [0, nx) read 0.
+            const int64_t xp = p0 + j;                       // (xp - p_start) mod L == j
             __syncthreads();
             store_stage((int)((xp + 1) & (S - 1)), rq[0]);   // plane xp+1
 #pragma unroll
@@ -345,14 +321,13 @@ hipError_t zpass_r(const void *in_, void *out_, Dims d, const Halo &h, const Tap
     const int64_t rows = h.NX * h.NY;
     const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     prof::Scope scope(kernel_name<St>("k_zpass_r", R), s);
-    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0) {
-        const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
-        hipLaunchKernelGGL((k_zpass_rows<R, St>), grid, dim3(kThreads), 0, s, in, out, rows, d.nz,
-                           h.NZ, (int64_t)h.hz, tz);
-    } else {
-        hipLaunchKernelGGL((k_zpass_r<R, St>), dim3((unsigned)rows, zt), dim3(kThreads), 0, s, in,
-                           out, d.nz, h.NZ, (int64_t)h.hz, tz);
-    }
+    const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
+    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0)
+        hipLaunchKernelGGL((k_zpass_rows<R, St, true>), grid, dim3(kThreads), 0, s, in, out, rows,
+                           d.nz, h.NZ, (int64_t)h.hz, tz);
+    else
+        hipLaunchKernelGGL((k_zpass_rows<R, St, false>), grid, dim3(kThreads), 0, s, in, out, rows,
+                           d.nz, h.NZ, (int64_t)h.hz, tz);
     return hipGetLastError();
 }
 
