@@ -33,6 +33,23 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, float v, uint32
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
 }
 
+// Two consecutive floats (8-byte aligned offset) in one access.
+typedef unsigned int gsf_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const gsf_u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, float a, float b, uint32_t off)
+{
+    gsf_u2 v;
+    v.x = __float_as_uint(a);
+    v.y = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+
 // ---- storage types ----
 // Cubes are stored as float (FP32), _Float16 (IEEE binary16) or __bf16
 // (bfloat16); kernels compute in FP32, widen on load (exact) and round to

@@ -83,11 +83,12 @@ hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo 
                           const Taps &txy, double *partials, int *nparts, hipStream_t s);
 
 // Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
-// bx in {8, 16, 32, 64}, bz <= 65.  ws G1, G2: two cubes of floats.
+// bx in {8, 16, 32, 64}, bz <= 65, planes of at most 2^27 voxels.  G: two
+// cubes of floats (the yz-window sums as interleaved pairs).
 bool stats_fast_path(Box b, Dims d);
 hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const double *shift,
-                             float *G1, float *G2, float *mean, float *stdev, uint64_t *mask,
-                             double k, hipStream_t s);
+                             float *G, float *mean, float *stdev, uint64_t *mask, double k,
+                             hipStream_t s);
 
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
 // Cubes passed as void * hold elements of storage type st.
@@ -106,7 +107,8 @@ hipError_t launch_mean(const void *F, Store st, Dims d, double *partials, double
 // shift[0] = (sum of n partials) / V, fixed order.
 hipError_t launch_mean_partials(const double *partials, int n, int64_t V, double *shift,
                                 hipStream_t s);
-// Local statistics and (optionally) the mask.  ws1..ws4: four scratch cubes.
+// Local statistics and (optionally) the mask.  ws1..ws4: four scratch cubes,
+// consecutive pieces of one workspace.
 hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *shift, float *ws1,
                         float *ws2, float *ws3, float *ws4, float *mean, float *stdev,
                         uint64_t *mask, double k, hipStream_t s);

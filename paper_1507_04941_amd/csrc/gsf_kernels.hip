@@ -372,8 +372,10 @@ hipError_t launch_stats(const void *F, Store st, Dims d, Box b, const double *sh
                         float *ws2, float *ws3, float *ws4, float *mean, float *stdev,
                         uint64_t *mask, double k, hipStream_t s)
 {
+    // ws1 .. ws4 are consecutive pieces of one workspace, each at least a
+    // cube: the fast path's pairs take ws1 and ws2 as one two-cube block
     if (stats_fast_path(b, d))
-        return launch_stats_fast(F, st, d, b, shift, ws1, ws2, mean, stdev, mask, k, s);
+        return launch_stats_fast(F, st, d, b, shift, ws1, mean, stdev, mask, k, s);
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
         const size_t zlds = 2 * (size_t)(kBlock + b.bz - 1) * sizeof(float);

@@ -8,7 +8,8 @@
 //     the last BY rows, so F is read once), then take the z window across the
 //     lanes of a 64-wide strip with DPP lane scans (k_box_yz_seg: the column
 //     sums pass through an LDS tile shared by the block's NW waves).
-//     Writes the yz-window sums G1 = sum a, G2 = sum a^2 for every voxel.
+//     Writes the yz-window sums G1 = sum a, G2 = sum a^2 for every voxel,
+//     interleaved (G[v] = {G1, G2}, one 8-byte access per voxel).
 //   k_box_x_select<BX>: one lane per (y, z) walks x with a running window sum
 //     of G1, G2 (leaving plane from a register ring of the last BX planes),
 //     then forms mean = s + S1/n and std = sqrt(max(0, S2/n - (S1/n)^2)),
@@ -103,8 +104,7 @@ template <int BY, typename St>
 __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, int64_t nx,
                                                      int64_t ny, int64_t nz, int bz,
                                                      const double *__restrict__ shift,
-                                                     float *__restrict__ G1,
-                                                     float *__restrict__ G2)
+                                                     float *__restrict__ G)
 {
     constexpr int AH = BY < kAhead ? BY : kAhead;   // prefetch depth, at most the ring length
     static_assert(BY % AH == 0, "ring length must be a multiple of the prefetch depth");
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
     const float s = (float)shift[0];
     constexpr int64_t SZ = sizeof(St);
     const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);     // G planes and rows (FP32)
-    const uint32_t row_b = (uint32_t)(nz * 4);
+    const uint32_t plane_b = (uint32_t)(plane * 8);     // G planes and rows (FP32 pairs)
+    const uint32_t row_b = (uint32_t)(nz * 8);
     const uint32_t fplane_b = (uint32_t)(plane * SZ);   // F planes and rows (storage type)
     const uint32_t frow_b = (uint32_t)(nz * SZ);
     // the two adjacent columns this lane carries: t = 2*lane and 2*lane + 1
@@ -137,9 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
     const uint32_t o1 = v1 ? (uint32_t)(zc1 * SZ) : kOOB;
     const __amdgpu_buffer_rsrc_t rf = buf(F + x * plane, fplane_b);
     const int64_t zo = z0 + lane;
-    const uint32_t og = zo < nz ? (uint32_t)(zo * 4) : kOOB;
-    const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
-    const __amdgpu_buffer_rsrc_t rg2 = buf(G2 + x * plane, plane_b);
+    const uint32_t og = zo < nz ? (uint32_t)(zo * 8) : kOOB;
+    const __amdgpu_buffer_rsrc_t rg = buf(G + 2 * x * plane, plane_b);
     float ring0[BY], ring1[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ring0[j] = ring1[j] = 0.0f;
@@ -179,9 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_box_yz(const St *__restrict__ F, i
             if (y >= 0 && y < ny) {
                 const float h1 = zwin(a1, b1, q1, lane, bz);
                 const float h2 = zwin(a2, b2, q2, lane, bz);
-                const uint32_t oy = og + (uint32_t)y * row_b;
-                buf_st(rg1, h1, oy);
-                buf_st(rg2, h2, oy);
+                buf_st2(rg, h1, h2, og + (uint32_t)y * row_b);
             }
             // look-ahead comes from the explicit prefetch, not from hoisting
             __builtin_amdgcn_sched_barrier(0);
@@ -281,8 +278,7 @@ template <int BY, int BZ, int NW, typename St>
 __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F, int64_t nx,
                                                         int64_t ny64, int64_t nz64,
                                                         const double *__restrict__ shift,
-                                                        float *__restrict__ G1,
-                                                        float *__restrict__ G2)
+                                                        float *__restrict__ G)
 {
 #pragma clang fp contract(off)
     constexpr int AH = BY < kAhead ? BY : kAhead;   // prefetch depth, at most the ring length
@@ -304,8 +300,8 @@ __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F
     const float s = (float)shift[0];
     constexpr uint32_t SZ = sizeof(St);
     const int64_t plane = (int64_t)ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * 4);     // G planes and rows (FP32)
-    const uint32_t row_b = (uint32_t)nz * 4u;
+    const uint32_t plane_b = (uint32_t)(plane * 8);     // G planes and rows (FP32 pairs)
+    const uint32_t row_b = (uint32_t)nz * 8u;
     const uint32_t frow_b = (uint32_t)nz * SZ;          // F rows (storage type)
     // the column this lane walks: tile column threadIdx.x
     const int zc = Z0 - 32 + (int)threadIdx.x;
@@ -318,11 +314,10 @@ __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F
     const int ia = 64 * wave + 32 - BZ / 2 + seg * BZ + (BZ - 1 - q);
     const int ib = ia + 2 * q + 1;
     const int zo = Z0 + 64 * wave + seg * BZ + (BZ - 1 - q);
-    const uint32_t og = out_wave && zo < nz ? (uint32_t)zo * 4u : kOOB;
+    const uint32_t og = out_wave && zo < nz ? (uint32_t)zo * 8u : kOOB;
     const bool has_head = q < BZ - 1;
     const int src = has_head ? seg * BZ + (BZ - 2 - q) : lane;
-    const __amdgpu_buffer_rsrc_t rg1 = buf(G1 + x * plane, plane_b);
-    const __amdgpu_buffer_rsrc_t rg2 = buf(G2 + x * plane, plane_b);
+    const __amdgpu_buffer_rsrc_t rg = buf(G + 2 * x * plane, plane_b);
     float ring[BY];
 #pragma unroll
     for (int j = 0; j < BY; ++j) ring[j] = 0.0f;
@@ -363,9 +358,8 @@ __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F
                                 __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
                             const float h2 = __int_as_float(
                                 __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
-                            const uint32_t oy = og + (uint32_t)y * row_b;
-                            buf_st(rg1, has_head ? t[0] + h1 : t[0], oy);
-                            buf_st(rg2, has_head ? t[1] + h2 : t[1], oy);
+                            buf_st2(rg, has_head ? t[0] + h1 : t[0], has_head ? t[1] + h2 : t[1],
+                                    og + (uint32_t)y * row_b);
                         }
                     }
                 }
@@ -421,7 +415,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const E *c, int p, 
 }
 
 // One lane per (y, z), 256 consecutive z per block; walks x.  Per step the
-// lane loads the entering plane's G1, G2 and the output plane's F (issued
+// lane loads the entering plane's {G1, G2} pair and the output plane's F (issued
 // kAheadX steps early), updates the FP64 window sums with the ring of the
 // last BX planes, and finishes the output plane.  Plane addressing is
 // 32-bit: every BX steps the kernel sets up descriptors over the next BX
@@ -429,7 +423,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const E *c, int p, 
 // needs BX + 1 planes to span less than 2^31 bytes.
 template <int BX, typename St, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
-    const float *__restrict__ G1, const float *__restrict__ G2, const St *__restrict__ F,
+    const float2 *__restrict__ G, const St *__restrict__ F,
     int64_t nx64, int64_t ny64, int64_t nz64, int by, int bz, const double *__restrict__ shift,
     float *__restrict__ mean, float *__restrict__ stdev, uint64_t *__restrict__ mask, double k)
 {
@@ -443,10 +437,12 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const bool live = z < nz;
     constexpr uint32_t SZ = sizeof(St);
     const uint32_t plane = (uint32_t)ny * (uint32_t)nz;
-    const uint32_t plane_b = plane * 4u;                 // G, mean, std (FP32)
+    const uint32_t plane_b = plane * 4u;                 // mean, std (FP32)
+    const uint32_t gplane_b = plane * 8u;                // G (FP32 pairs)
     const uint32_t fplane_b = plane * SZ;                // F (storage type)
     // offset of (y, z) inside a plane; dead lanes address outside every range
     const uint32_t off = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * 4u : kOOB;
+    const uint32_t offg = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * 8u : kOOB;
     const uint32_t offf = live ? ((uint32_t)y * (uint32_t)nz + (uint32_t)z) * SZ : kOOB;
     const int W = (nz + 63) / 64;
     const int hix = -(BX / 2) + BX - 1;
@@ -461,17 +457,15 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
     // loads issued AX steps early: plane pa of G (entering) and plane
     // pa - hix of F (output)
-    float pg1[AX], pg2[AX];
+    float2 pg[AX];
     raw_t<St> pfv[AX];
     {
-        const __amdgpu_buffer_rsrc_t q1 = plane_span(G1, 0, AX, nx, plane);
-        const __amdgpu_buffer_rsrc_t q2 = plane_span(G2, 0, AX, nx, plane);
+        const __amdgpu_buffer_rsrc_t qg = plane_span(G, 0, AX, nx, plane);
         const __amdgpu_buffer_rsrc_t qf = plane_span(F, 0, AX, nx, plane);
 #pragma unroll
         for (int j = 0; j < AX; ++j) {
             const int xf = j - hix;
-            pg1[j] = buf_ld(q1, off + (uint32_t)j * plane_b);
-            pg2[j] = buf_ld(q2, off + (uint32_t)j * plane_b);
+            pg[j] = buf_ld2(qg, offg + (uint32_t)j * gplane_b);
             pfv[j] = sbuf_ld_raw<St>(qf, offf + (uint32_t)(xf >= 0 ? xf : BX) * fplane_b);
         }
     }
@@ -492,18 +486,16 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
         const int xo = p0 - hix;
         const int xb = xo > 0 ? xo : 0;
         const uint32_t pb = opaque(plane_b);
+        const uint32_t pbg = opaque(gplane_b);
         const uint32_t pbf = opaque(fplane_b);
-        const __amdgpu_buffer_rsrc_t rg1 = plane_span(G1, ga, BX, nx, plane);
-        const __amdgpu_buffer_rsrc_t rg2 = plane_span(G2, ga, BX, nx, plane);
+        const __amdgpu_buffer_rsrc_t rg = plane_span(G, ga, BX, nx, plane);
         const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane);
 #pragma clang loop unroll(full)
         for (int j = 0; j < BX; ++j) {
-            const float g1 = pg1[j % AX], g2 = pg2[j % AX];
+            const float g1 = pg[j % AX].x, g2 = pg[j % AX].y;
             const raw_t<St> fraw = pfv[j % AX];
             const int xf = fa + j;
-            const uint32_t og = off + (uint32_t)j * pb;
-            pg1[j % AX] = buf_ld(rg1, og);
-            pg2[j % AX] = buf_ld(rg2, og);
+            pg[j % AX] = buf_ld2(rg, offg + (uint32_t)j * pbg);
             pfv[j % AX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
             s1 += (double)g1 - (double)r1[j];
             s2 += (double)g2 - (double)r2[j];
@@ -572,7 +564,7 @@ const char *x_name(int bx)
 }
 
 template <int BY, int NW, typename St>
-hipError_t yz_seg(const St *F, Dims d, int bz, const double *shift, float *G1, float *G2,
+hipError_t yz_seg(const St *F, Dims d, int bz, const double *shift, float *G,
                   hipStream_t s)
 {
     constexpr int NO = 64 * (NW - 1);
@@ -580,18 +572,18 @@ hipError_t yz_seg(const St *F, Dims d, int bz, const double *shift, float *G1, f
     const dim3 block(64 * NW);
     if (bz == 16)
         hipLaunchKernelGGL((k_box_yz_seg<BY, 16, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
-                           shift, G1, G2);
+                           shift, G);
     else if (bz == 32)
         hipLaunchKernelGGL((k_box_yz_seg<BY, 32, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
-                           shift, G1, G2);
+                           shift, G);
     else
         hipLaunchKernelGGL((k_box_yz_seg<BY, 64, NW, St>), grid, block, 0, s, F, d.nx, d.ny, d.nz,
-                           shift, G1, G2);
+                           shift, G);
     return hipGetLastError();
 }
 
 template <int BY, typename St>
-hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G1, float *G2,
+hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G,
                   hipStream_t s)
 {
     const St *F = (const St *)F_;
@@ -605,36 +597,37 @@ hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G1
             const int64_t c = (d.nz + 64 * (nw - 1) - 1) / (64 * (nw - 1)) * nw;
             if (nw == 9 || c < cost) best = nw, cost = c;
         }
-        if (best == 3) return yz_seg<BY, 3, St>(F, d, bz, shift, G1, G2, s);
-        if (best == 5) return yz_seg<BY, 5, St>(F, d, bz, shift, G1, G2, s);
-        return yz_seg<BY, 9, St>(F, d, bz, shift, G1, G2, s);
+        if (best == 3) return yz_seg<BY, 3, St>(F, d, bz, shift, G, s);
+        if (best == 5) return yz_seg<BY, 5, St>(F, d, bz, shift, G, s);
+        return yz_seg<BY, 9, St>(F, d, bz, shift, G, s);
     }
     const int64_t jobs = d.nx * ((d.nz + 63) / 64);
     hipLaunchKernelGGL((k_box_yz<BY, St>), dim3((unsigned)((jobs + 3) / 4)), dim3(kThreads), 0, s,
-                       F, d.nx, d.ny, d.nz, bz, shift, G1, G2);
+                       F, d.nx, d.ny, d.nz, bz, shift, G);
     return hipGetLastError();
 }
 
 template <int BX, typename St>
-hipError_t box_x_select(const float *G1, const float *G2, const void *F, Dims d, Box b,
+hipError_t box_x_select(const float *G, const void *F, Dims d, Box b,
                         const double *shift, float *mean, float *stdev, uint64_t *mask, double k,
                         hipStream_t s)
 {
     const dim3 grid((unsigned)((d.nz + kThreads - 1) / kThreads), (unsigned)d.ny);
     prof::Scope scope(x_name<St>(BX), s);
     if (mean || stdev)
-        hipLaunchKernelGGL((k_box_x_select<BX, St, true>), grid, dim3(kThreads), 0, s, G1, G2,
+        hipLaunchKernelGGL((k_box_x_select<BX, St, true>), grid, dim3(kThreads), 0, s,
+                           (const float2 *)G,
                            (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
     else
-        hipLaunchKernelGGL((k_box_x_select<BX, St, false>), grid, dim3(kThreads), 0, s, G1, G2,
+        hipLaunchKernelGGL((k_box_x_select<BX, St, false>), grid, dim3(kThreads), 0, s,
+                           (const float2 *)G,
                            (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
     return hipGetLastError();
 }
 
-using YZFn = hipError_t (*)(const void *, Dims, int, const double *, float *, float *,
-                            hipStream_t);
-using XFn = hipError_t (*)(const float *, const float *, const void *, Dims, Box, const double *,
-                           float *, float *, uint64_t *, double, hipStream_t);
+using YZFn = hipError_t (*)(const void *, Dims, int, const double *, float *, hipStream_t);
+using XFn = hipError_t (*)(const float *, const void *, Dims, Box, const double *, float *,
+                           float *, uint64_t *, double, hipStream_t);
 
 template <typename St>
 YZFn yz_fn(int by)
@@ -664,22 +657,25 @@ XFn x_fn(int bx)
 
 bool stats_fast_path(Box b, Dims d)
 {
-    // the x walk addresses BX + 1 planes with 32-bit offsets
-    const bool x_fits = (int64_t)(b.bx + 1) * d.ny * d.nz * 4 < ((int64_t)1 << 31);
-    return yz_fn<float>(b.by) && x_fn<float>(b.bx) && b.bz >= 1 && b.bz <= 65 && plane_fits(d) &&
-           x_fits;
+    // the x walk addresses BX + 1 planes of 8-byte pairs with 32-bit offsets;
+    // a plane of pairs stays below 2^30 bytes so that a dead lane's offset
+    // (2^31) plus a row or plane offset never wraps into range
+    const int64_t plane = d.ny * d.nz;
+    const bool x_fits = (int64_t)(b.bx + 1) * plane * 8 < ((int64_t)1 << 31);
+    return yz_fn<float>(b.by) && x_fn<float>(b.bx) && b.bz >= 1 && b.bz <= 65 &&
+           plane <= ((int64_t)1 << 27) && x_fits;
 }
 
 hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const double *shift,
-                             float *G1, float *G2, float *mean, float *stdev, uint64_t *mask,
+                             float *G, float *mean, float *stdev, uint64_t *mask,
                              double k, hipStream_t s)
 {
     if (!stats_fast_path(b, d)) return hipErrorInvalidValue;
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
-        hipError_t e = yz_fn<St>(b.by)(F, d, b.bz, shift, G1, G2, s);
+        hipError_t e = yz_fn<St>(b.by)(F, d, b.bz, shift, G, s);
         if (e != hipSuccess) return e;
-        return x_fn<St>(b.bx)(G1, G2, F, d, b, shift, mean, stdev, mask, k, s);
+        return x_fn<St>(b.bx)(G, F, d, b, shift, mean, stdev, mask, k, s);
     });
 }
 
