@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <utility>
 #include <string>
 
 #include "gsf_device.h"
@@ -327,45 +328,68 @@ __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F
     double c1 = 0.0, c2 = 0.0;                      // running y sums of the column
     const int nsteps = ny + hiy;
     int bsel = 0;                                   // tile buffer of the current rows
+    // A ring turn is unrolled as NQ chunks of YQ steps (whole exchange
+    // groups); the walk leaves after the first chunk that reaches nsteps, so
+    // at most YQ - 1 surplus steps run.  The exits leave the loop (uniform
+    // over the block), so the steps carry no branch around their loads.
+    constexpr int YQ = BY / 4 > YB ? BY / 4 : YB;
+    constexpr int NQ = BY / YQ;
+    static_assert(NQ == 1 || NQ == 2 || NQ == 4, "chunks per turn");
 #pragma nounroll
-    for (int y0 = 0; y0 < nsteps; y0 += BY) {
+    for (int y0 = 0;; y0 += BY) {
+        auto chunk = [&](auto cc) __attribute__((always_inline)) {
+            constexpr int c = decltype(cc)::value;
 #pragma clang loop unroll(full)
-        for (int j = 0; j < BY; ++j) {
-            const int yin = y0 + j;                       // yin mod BY == j
-            // rows past ny and columns outside [0, nz) count as 0 (their
-            // loads read 0 through the range check)
-            const float e = from_raw<St>(pf[j % AH]) - s;
-            const float ev = yin < ny && oc != kOOB ? e : 0.0f;
-            pf[j % AH] = sbuf_ld_raw<St>(rf, oc + (uint32_t)(yin + AH) * frow_b);
-            const float l = ring[j];
-            ring[j] = ev;
-            c1 += (double)(ev - l);
-            c2 += (double)(ev * ev - l * l);
-            hs[bsel][j % YB][threadIdx.x] = make_float2((float)c1, (float)c2);
-            if (j % YB == YB - 1) {
-                // rows yin-YB+1 .. yin are in the tile; the other buffer was
-                // last read before this barrier's predecessor
-                __syncthreads();
-                if (out_wave) {
-#pragma unroll
-                    for (int r = 0; r < YB; ++r) {
-                        const int y = yin - (YB - 1) + r - hiy;
-                        if (y >= 0 && y < ny) {
-                            const float2 a = hs[bsel][r][ia], b = hs[bsel][r][ib];
-                            float t[4] = {a.x, a.y, b.x, b.y};
-                            seg_scan4<BZ>(t);
-                            const float h1 = __int_as_float(
-                                __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
-                            const float h2 = __int_as_float(
-                                __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
-                            buf_st2(rg, has_head ? t[0] + h1 : t[0], has_head ? t[1] + h2 : t[1],
-                                    og + (uint32_t)y * row_b);
+            for (int jj = 0; jj < YQ; ++jj) {
+                const int j = c * YQ + jj;
+                    const int yin = y0 + j;                       // yin mod BY == j
+                    // rows past ny and columns outside [0, nz) count as 0 (their
+                    // loads read 0 through the range check)
+                    const float e = from_raw<St>(pf[j % AH]) - s;
+                    const float ev = yin < ny && oc != kOOB ? e : 0.0f;
+                    pf[j % AH] = sbuf_ld_raw<St>(rf, oc + (uint32_t)(yin + AH) * frow_b);
+                    const float l = ring[j];
+                    ring[j] = ev;
+                    c1 += (double)(ev - l);
+                    c2 += (double)(ev * ev - l * l);
+                    hs[bsel][j % YB][threadIdx.x] = make_float2((float)c1, (float)c2);
+                    if (j % YB == YB - 1) {
+                        // rows yin-YB+1 .. yin are in the tile; the other buffer was
+                        // last read before this barrier's predecessor
+                        __syncthreads();
+                        if (out_wave) {
+        #pragma unroll
+                            for (int r = 0; r < YB; ++r) {
+                                const int y = yin - (YB - 1) + r - hiy;
+                                if (y >= 0 && y < ny) {
+                                    const float2 a = hs[bsel][r][ia], b = hs[bsel][r][ib];
+                                    float t[4] = {a.x, a.y, b.x, b.y};
+                                    seg_scan4<BZ>(t);
+                                    const float h1 = __int_as_float(
+                                        __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[2])));
+                                    const float h2 = __int_as_float(
+                                        __builtin_amdgcn_ds_bpermute(src * 4, __float_as_int(t[3])));
+                                    buf_st2(rg, has_head ? t[0] + h1 : t[0], has_head ? t[1] + h2 : t[1],
+                                            og + (uint32_t)y * row_b);
+                                }
+                            }
                         }
+                        bsel ^= 1;
                     }
-                }
-                bsel ^= 1;
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+        };
+        chunk(std::integral_constant<int, 0>{});
+        if (y0 + YQ >= nsteps) break;
+        if constexpr (NQ > 1) {
+            chunk(std::integral_constant<int, 1>{});
+            if (y0 + 2 * YQ >= nsteps) break;
+        }
+        if constexpr (NQ > 2) {
+            chunk(std::integral_constant<int, 2>{});
+            if (y0 + 3 * YQ >= nsteps) break;
+            chunk(std::integral_constant<int, 3>{});
+            if (y0 + 4 * YQ >= nsteps) break;
         }
     }
 }
