@@ -122,6 +122,26 @@ def cpu_baseline(w, d, target_s: float):
     }
 
 
+def copy_bandwidth(device, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s (bytes read + written) of a plain 1 GiB device copy: the rate this
+    GPU reaches on a streaming kernel, beside the 8 TB/s datasheet peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=device).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(device, nbytes: int = 1 << 30, reps: int = 3) -> None:
     """Plain device copy of known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -215,6 +235,16 @@ def main() -> int:
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
                     "algorithmic_bytes_per_launch": alg, "share_of_step": round(ms / total_ms, 3)}
+            if traffic is not None:
+                roof["traffic_over_algorithmic"] = round(traffic / alg, 4)
+            copy_gbs = copy_bandwidth(dev)
+            roof["copy_gbs"] = round(copy_gbs, 1)
+            roof["frac_of_copy"] = round(ach / copy_gbs, 4)
+            print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    for k, (n, ms) in kern.items():
+        a = algorithmic_bytes(k, V)
+        if a is not None:
+            kernels[k]["algorithmic_gbs"] = round(a / (ms / n * 1e-3) / 1e9, 1)
 
     # the same step with the cube, T1 and F stored in 16 bits (window sums FP32)
     storage16 = {}
