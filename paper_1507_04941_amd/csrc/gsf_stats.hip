@@ -394,17 +394,6 @@ __global__ __launch_bounds__(64 * NW) void k_box_yz_seg(const St *__restrict__ F
     }
 }
 
-// 1/c for window lengths c = 0..64 (entry 0 unused).
-__constant__ double kInv[65] = {
-    0.0,       1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,
-    1.0 / 9,   1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17,
-    1.0 / 18,  1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26,
-    1.0 / 27,  1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33, 1.0 / 34, 1.0 / 35,
-    1.0 / 36,  1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44,
-    1.0 / 45,  1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53,
-    1.0 / 54,  1.0 / 55, 1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62,
-    1.0 / 63,  1.0 / 64};
-
 __device__ __forceinline__ int win_len32(int i, int n, int B)
 {
     int lo = i - (B / 2);
@@ -473,9 +462,13 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const double s = (double)(float)shift[0];   // the same FP32 shift the sums used
     const double inv_yz =
         live ? 1.0 / (double)(win_len(y, ny, by) * win_len(z, nz, bz)) : 1.0;
-    const int64_t mstride = (int64_t)ny * W;
-    // this wave's mask word of plane 0 (wave-uniform); plane x adds x * mstride
-    uint64_t *mrow = mask ? mask + (int64_t)y * W + blockIdx.x * (kThreads / 64) + wave : nullptr;
+    // this wave's mask word of plane 0 (wave-uniform, bytes); plane x adds
+    // x * mplane_b.  The mask array is below 2^31 bytes (checked on the host).
+    const uint32_t mplane_b = (uint32_t)ny * (uint32_t)W * 8u;
+    const uint32_t mword_b =
+        ((uint32_t)y * (uint32_t)W + blockIdx.x * (kThreads / 64) + (uint32_t)wave) * 8u;
+    const __amdgpu_buffer_rsrc_t rmask =
+        buf(mask, mask ? (uint32_t)nx * mplane_b : 0u);
     float r1[BX], r2[BX];
 #pragma unroll
     for (int j = 0; j < BX; ++j) r1[j] = r2[j] = 0.0f;
@@ -531,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
                 // from the x faces cx = BX and 1/BX is exact
                 const int cx = win_len32(x, nx, BX);
                 double icx = 1.0 / BX;
-                if (cx != BX) icx = kInv[cx];
+                if (cx != BX) icx = 1.0 / (double)cx;   // IEEE division: correctly rounded
                 const double inv_n = inv_yz * icx;
                 const double m1 = s1 * inv_n;
                 double var = s2 * inv_n - m1 * m1;
@@ -543,11 +536,14 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
                     if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
                     if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
                 }
-                if (mrow) {
+                if (mask) {
                     const float fv = from_raw<St>(fraw);
                     const bool bit = live && (double)fv > (double)mf + k * (double)sf;
                     const uint64_t word = __ballot(bit);
-                    if ((threadIdx.x & 63) == 0 && live) mrow[(int64_t)x * mstride] = word;
+                    if ((threadIdx.x & 63) == 0 && live)
+                        buf_st2(rmask, __uint_as_float((uint32_t)word),
+                                __uint_as_float((uint32_t)(word >> 32)),
+                                mword_b + (uint32_t)x * mplane_b);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -686,8 +682,10 @@ bool stats_fast_path(Box b, Dims d)
     // (2^31) plus a row or plane offset never wraps into range
     const int64_t plane = d.ny * d.nz;
     const bool x_fits = (int64_t)(b.bx + 1) * plane * 8 < ((int64_t)1 << 31);
+    // the mask words are stored with 32-bit byte offsets
+    const bool mask_fits = d.nx * d.ny * ((d.nz + 63) / 64) * 8 < ((int64_t)1 << 31);
     return yz_fn<float>(b.by) && x_fn<float>(b.bx) && b.bz >= 1 && b.bz <= 65 &&
-           plane <= ((int64_t)1 << 27) && x_fits;
+           plane <= ((int64_t)1 << 27) && x_fits && mask_fits;
 }
 
 hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const double *shift,
