@@ -276,20 +276,33 @@ gsf_status gsf_filter3d_weighted(const void *in, const void *w, gsf_dtype t, gsf
     const gsf::Dims dd = to_dims(d);
     const gsf::Halo h = gsf::no_halo(dd);
     const hipStream_t s = (hipStream_t)stream;
-    // [P = d*w][T1][D][generic-path scratch]; N goes to out
+    // [P = d*w][T1][D][generic-path scratch]; N goes to out.  Where the radii
+    // have compiled forms the product is formed inside the first spectral
+    // pass and the quotient inside the last sweep (P and D stay unused).
     const size_t c = cube_bytes(d);
     float *P = (float *)ws;
     float *T1 = (float *)((char *)ws + c);
     float *D = (float *)((char *)ws + 2 * c);
     void *tmp = (char *)ws + 3 * c;
-    hipError_t e = gsf::launch_mul((const float *)in, (const float *)w, P, dd.voxels(), s);
-    if (e == hipSuccess) e = gsf::launch_zpass(P, T1, gsf::Store::F32, dd, h, tz, s);
+    const bool fused = gsf::zpass_fast(tz.r) && gsf::yx_fast(txy.r, dd);
+    hipError_t e;
+    if (fused) {
+        e = gsf::launch_zpass_mul_fast((const float *)in, (const float *)w, T1, dd, tz, s);
+    } else {
+        e = gsf::launch_mul((const float *)in, (const float *)w, P, dd.voxels(), s);
+        if (e == hipSuccess) e = gsf::launch_zpass(P, T1, gsf::Store::F32, dd, h, tz, s);
+    }
     if (e == hipSuccess)
         e = gsf::launch_yx(T1, out, tmp, gsf::Store::F32, dd, h, txy, nullptr, nullptr, s);
     if (e == hipSuccess) e = gsf::launch_zpass(w, T1, gsf::Store::F32, dd, h, tz, s);
-    if (e == hipSuccess)
-        e = gsf::launch_yx(T1, D, tmp, gsf::Store::F32, dd, h, txy, nullptr, nullptr, s);
-    if (e == hipSuccess) e = gsf::launch_div((const float *)out, D, (float *)out, dd.voxels(), s);
+    if (fused) {
+        if (e == hipSuccess) e = gsf::launch_yx_div_fast(T1, (float *)out, dd, txy, s);
+    } else {
+        if (e == hipSuccess)
+            e = gsf::launch_yx(T1, D, tmp, gsf::Store::F32, dd, h, txy, nullptr, nullptr, s);
+        if (e == hipSuccess)
+            e = gsf::launch_div((const float *)out, D, (float *)out, dd.voxels(), s);
+    }
     return device_status(e, "gsf_filter3d_weighted launch");
 }
 

@@ -70,13 +70,15 @@ __device__ __forceinline__ void store4(St *p, const float (&v)[4])
 // and a lane loads and stores its four values with single 4-element
 // accesses; otherwise it uses element accesses through range-checked buffer
 // descriptors (values past the row read 0, stores past it are dropped).
+// With MUL the pass filters the voxel-wise product in * wv (FP32 products,
+// as a separate multiply would store them): the weighted numerator of Eq. 1.
 constexpr int kZRows = 16;
 
-template <int R, typename St, bool A>
+template <int R, typename St, bool A, bool MUL = false>
 __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
                                                          St *__restrict__ out, int64_t nrows,
                                                          int64_t nz, int64_t NZ, int64_t zoff,
-                                                         Taps t)
+                                                         Taps t, const St *__restrict__ wv = nullptr)
 {
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
     constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
@@ -99,18 +101,31 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
     const uint32_t om = (uint32_t)((zm + zoff) * SZ);
     const uint32_t oh = halo ? (uint32_t)((zh + zoff) * SZ) : kOOB;
     const uint32_t os = (uint32_t)(zm * SZ);
-    auto fetch = [&](int64_t r, float4 &m, float &h) {
+    auto fetch_one = [&](const St *src, int64_t r, float4 &m, float &h) {
         if constexpr (A) {
-            const St *row = in + r * NZ + zoff;
+            const St *row = src + r * NZ + zoff;
             m = load ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
             h = halo ? widen(row[zh]) : 0.0f;
         } else {
-            const __amdgpu_buffer_rsrc_t rr = buf(in + r * NZ, (uint32_t)(NZ * SZ));
+            const __amdgpu_buffer_rsrc_t rr = buf(src + r * NZ, (uint32_t)(NZ * SZ));
             m.x = sbuf_ld<St>(rr, om);
             m.y = sbuf_ld<St>(rr, om + SZ);
             m.z = sbuf_ld<St>(rr, om + 2 * SZ);
             m.w = sbuf_ld<St>(rr, om + 3 * SZ);
             h = sbuf_ld<St>(rr, oh);
+        }
+    };
+    auto fetch = [&](int64_t r, float4 &m, float &h) {
+        fetch_one(in, r, m, h);
+        if constexpr (MUL) {
+            float4 mw;
+            float hw;
+            fetch_one(wv, r, mw, hw);
+            m.x *= mw.x;
+            m.y *= mw.y;
+            m.z *= mw.z;
+            m.w *= mw.w;
+            h *= hw;
         }
     };
     float4 m;
@@ -152,9 +167,12 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
     }
 }
 
-template <int R, int P, int NW, typename St>
+// With DIV, F holds the numerator N of Eq. 1 on entry and the sweep's
+// result D is not stored: each output becomes N / D (0 where D = 0), read
+// and written in place by the same lane.
+template <int R, int P, int NW, typename St, bool DIV = false>
 __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
-                                                  St *__restrict__ F, int64_t nx, int64_t ny,
+                                                  St *F, int64_t nx, int64_t ny,
                                                   int64_t nz, int64_t xchunk, Taps t,
                                                   double *__restrict__ partials, int64_t NX,
                                                   int64_t NY, int64_t hx, int64_t hy)
@@ -271,10 +289,17 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
                 const __amdgpu_buffer_rsrc_t rf = buf(F + xo * plane, plane_b);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    // the shift sums the stored (rounded) values
-                    const float v = widen(narrow<St>(acc[q][slot_o]));
-                    sbuf_st<St>(rf, v, st0 + (uint32_t)q * row_b);
-                    if (zl && y0 + q < ny) fsum += (double)v;
+                    if constexpr (DIV) {
+                        const uint32_t o = st0 + (uint32_t)q * row_b;
+                        const float den = acc[q][slot_o];
+                        const float num = sbuf_ld<St>(rf, o);
+                        sbuf_st<St>(rf, den != 0.0f ? num / den : 0.0f, o);
+                    } else {
+                        // the shift sums the stored (rounded) values
+                        const float v = widen(narrow<St>(acc[q][slot_o]));
+                        sbuf_st<St>(rf, v, st0 + (uint32_t)q * row_b);
+                        if (zl && y0 + q < ny) fsum += (double)v;
+                    }
                 }
             }
 #pragma unroll
@@ -312,26 +337,34 @@ const char *kernel_name(const char *base, int r)
     return tab[base[2] == 'z' ? 0 : 1][r].c_str();
 }
 
-template <int R, typename St>
-hipError_t zpass_r(const void *in_, void *out_, Dims d, const Halo &h, const Taps &tz,
-                   hipStream_t s)
+template <int R, typename St, bool MUL>
+hipError_t zpass_impl(const void *in_, void *out_, Dims d, const Halo &h, const Taps &tz,
+                      hipStream_t s, const void *w_)
 {
     const St *in = (const St *)in_;
+    const St *w = (const St *)w_;
     St *out = (St *)out_;
     const int64_t rows = h.NX * h.NY;
     const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
-    prof::Scope scope(kernel_name<St>("k_zpass_r", R), s);
+    prof::Scope scope(MUL ? "k_zpass_r_mul" : kernel_name<St>("k_zpass_r", R), s);
     const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
     if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0)
-        hipLaunchKernelGGL((k_zpass_rows<R, St, true>), grid, dim3(kThreads), 0, s, in, out, rows,
-                           d.nz, h.NZ, (int64_t)h.hz, tz);
+        hipLaunchKernelGGL((k_zpass_rows<R, St, true, MUL>), grid, dim3(kThreads), 0, s, in, out,
+                           rows, d.nz, h.NZ, (int64_t)h.hz, tz, w);
     else
-        hipLaunchKernelGGL((k_zpass_rows<R, St, false>), grid, dim3(kThreads), 0, s, in, out, rows,
-                           d.nz, h.NZ, (int64_t)h.hz, tz);
+        hipLaunchKernelGGL((k_zpass_rows<R, St, false, MUL>), grid, dim3(kThreads), 0, s, in, out,
+                           rows, d.nz, h.NZ, (int64_t)h.hz, tz, w);
     return hipGetLastError();
 }
 
-template <int R, int P, int NW, typename St>
+template <int R, typename St>
+hipError_t zpass_r(const void *in, void *out, Dims d, const Halo &h, const Taps &tz,
+                   hipStream_t s)
+{
+    return zpass_impl<R, St, false>(in, out, d, h, tz, s, nullptr);
+}
+
+template <int R, int P, int NW, typename St, bool DIV = false>
 hipError_t yx_r(const void *T, void *F, Dims d, const Halo &h, const Taps &txy, double *partials,
                 int *nparts, hipStream_t s)
 {
@@ -349,8 +382,10 @@ hipError_t yx_r(const void *T, void *F, Dims d, const Halo &h, const Taps &txy, 
     const int64_t blocks = tz * ty * nxc;
     if (!partials || blocks > kMaxPartials) partials = nullptr;
     if (nparts) *nparts = partials ? (int)blocks : 0;
-    prof::Scope scope(kernel_name<St>("k_yx_r", R), s);
-    hipLaunchKernelGGL((k_yx_r<R, P, NW, St>), grid, dim3(64 * NW), 0, s, (const St *)T, (St *)F,
+    if (DIV) partials = nullptr;
+    if (nparts && DIV) *nparts = 0;
+    prof::Scope scope(DIV ? "k_yx_r_div" : kernel_name<St>("k_yx_r", R), s);
+    hipLaunchKernelGGL((k_yx_r<R, P, NW, St, DIV>), grid, dim3(64 * NW), 0, s, (const St *)T, (St *)F,
                        d.nx, d.ny, d.nz, xchunk, txy, partials, h.NX, h.NY, (int64_t)h.hx,
                        (int64_t)h.hy);
     return hipGetLastError();
@@ -385,6 +420,25 @@ const YXFn *yxtab_of(std::integer_sequence<int, R...>)
     return tab;
 }
 
+// FP32 forms for the weighted convolution (Eq. 1): the spectral pass of the
+// product d * w and the spatial sweep that ends in the quotient.
+using ZMulFn = hipError_t (*)(const void *, void *, Dims, const Halo &, const Taps &, hipStream_t,
+                              const void *);
+
+template <int... R>
+const ZMulFn *zmultab_of(std::integer_sequence<int, R...>)
+{
+    static const ZMulFn tab[] = {nullptr, &zpass_impl<R + 1, float, true>...};
+    return tab;
+}
+
+template <int... R>
+const YXFn *yxdivtab_of(std::integer_sequence<int, R...>)
+{
+    static const YXFn tab[] = {nullptr, &yx_r<R + 1, yx_rows<R + 1>(), 8, float, true>...};
+    return tab;
+}
+
 }  // namespace
 
 bool zpass_fast(int rz) { return rz >= 1 && rz <= kMaxFastRz; }
@@ -401,6 +455,21 @@ hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const H
     case Store::BF16: return ztab_of<__bf16>(seq)[tz.r](in, T1, d, h, tz, s);
     default: return ztab_of<float>(seq)[tz.r](in, T1, d, h, tz, s);
     }
+}
+
+hipError_t launch_zpass_mul_fast(const float *in, const float *w, float *T1, Dims d,
+                                 const Taps &tz, hipStream_t s)
+{
+    if (!zpass_fast(tz.r)) return hipErrorInvalidValue;
+    return zmultab_of(std::make_integer_sequence<int, kMaxFastRz>{})[tz.r](
+        in, T1, d, no_halo(d), tz, s, w);
+}
+
+hipError_t launch_yx_div_fast(const float *T1, float *F, Dims d, const Taps &txy, hipStream_t s)
+{
+    if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
+    return yxdivtab_of(std::make_integer_sequence<int, kMaxFastRxy>{})[txy.r](
+        T1, F, d, no_halo(d), txy, nullptr, nullptr, s);
 }
 
 hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,

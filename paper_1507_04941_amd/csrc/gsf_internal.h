@@ -81,6 +81,13 @@ hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const H
                              const Taps &tz, hipStream_t s);
 hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,
                           const Taps &txy, double *partials, int *nparts, hipStream_t s);
+// FP32 weighted convolution (Eq. 1) pieces, no halo; hipErrorInvalidValue
+// when the radius has no compiled form.  T1 = gz * (in * w) along z; and
+// F = F / (gxy * (gxy * T1 along y) along x), 0 where the divisor is 0, in
+// place (F holds the numerator on entry).
+hipError_t launch_zpass_mul_fast(const float *in, const float *w, float *T1, Dims d,
+                                 const Taps &tz, hipStream_t s);
+hipError_t launch_yx_div_fast(const float *T1, float *F, Dims d, const Taps &txy, hipStream_t s);
 
 // Window lengths with compiled fast statistics paths (gsf_stats.hip): by and
 // bx in {8, 16, 32, 64}, bz <= 65, planes of at most 2^27 voxels.  G: two
