@@ -32,7 +32,8 @@ def _weights(shape, seed, flag_channels=False, zero_frac=0.0):
 @pytest.mark.parametrize("shape,f,kind", [
     ((40, 36, 140), (1.0, 2.0), "random"), ((33, 17, 300), (2.0, 8.0), "flagged"),
     ((20, 24, 77), (1.5, 2.5), "sparse"), ((64, 64, 128), (2.0, 4.0), "unit"),
-    ((9, 11, 50), (6.0, 11.0), "random")])      # generic passes
+    ((9, 11, 50), (6.0, 11.0), "random"),       # generic passes
+    ((12, 12, 90), (6.0, 1.0), "flagged")])     # compiled spectral pass, generic spatial passes
 def test_weighted_matches_oracle(shape, f, kind):
     log(f"weighted shape={shape} filter={f} weights={kind}")
     d = synth.make_cube(shape, n_sources=3, seed=sum(shape))
