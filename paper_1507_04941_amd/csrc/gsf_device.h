@@ -50,6 +50,20 @@ __device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, float a, float
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
 }
 
+// Four consecutive floats (16-byte aligned offset) in one store.
+typedef unsigned int gsf_u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void buf_st4(__amdgpu_buffer_rsrc_t r, float a, float b, float c,
+                                        float d, uint32_t off)
+{
+    gsf_u4 v;
+    v.x = __float_as_uint(a);
+    v.y = __float_as_uint(b);
+    v.z = __float_as_uint(c);
+    v.w = __float_as_uint(d);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+
 // ---- storage types ----
 // Cubes are stored as float (FP32), _Float16 (IEEE binary16) or __bf16
 // (bfloat16); kernels compute in FP32, widen on load (exact) and round to
