@@ -1,0 +1,54 @@
+"""GPU parity at the measured size with binary16 storage: the 512x512x1024
+cube rounded to binary16, the six-filter bank and 64^3 boxes, in the launch
+configuration the benchmark times for its FP16 line (one gsf_find over all
+filters, the cube, the spectral intermediate and F stored in binary16).
+Every voxel of F, the local mean and std and the mask of each filter is
+compared with the FP64 oracle run on the same rounded cube, to the 16-bit
+bounds of the parity helpers."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1507_04941_amd import binding as B
+from paper_1507_04941_amd import synth
+from tests.parity import (REL16, REL16_F, check_filtered, check_mask, check_stats, cube_scale,
+                          log, round16, sigma_f)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+W = synth.LARGE
+
+
+@pytest.fixture(scope="module")
+def large16():
+    log(f"full size f16: generating {W.name}")
+    d16 = round16(synth.workload_cube(W), "f16")
+    g = torch.from_numpy(d16).to(DEV).to(torch.float16)
+    log("full size f16: gsf_find with F, mean and std")
+    out = B.find(g, W.filters, W.box, W.k, want_F=True, want_stats=True)
+    torch.cuda.synchronize()
+    yield d16, out
+    del out, g
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("j", range(len(W.filters)))
+def test_every_voxel_matches_oracle_f16(large16, j):
+    d16, out = large16
+    f = W.filters[j]
+    log(f"full size f16 filter {f}: oracle")
+    ref = oracle.find(d16, [f], W.box, W.k, want_F=True, want_stats=True)
+    scale = cube_scale(d16)
+    Fg = out["F"][0][j].to(torch.float32).cpu().numpy()
+    wf = check_filtered(Fg, ref["F"][0], f, scale, what="F f16", rel=REL16_F["f16"])
+    wm, ws = check_stats(out["mean"][0][j].cpu().numpy(), out["std"][0][j].cpu().numpy(),
+                         ref["mean"][0], ref["std"][0], sigma_f(f) * scale, what="stats f16",
+                         rel=REL16["f16"])
+    mask_g = B.unpack_mask(out["mask"][0][j], d16.shape)
+    band = check_mask(mask_g, ref["F"][0], ref["mean"][0], ref["std"][0], W.k, f, scale,
+                      what="mask f16", rel=REL16["f16"], rel_f=REL16_F["f16"])
+    log(f"  F/bound={wf:.3g} mean/bound={wm:.3g} std/bound={ws:.3g} "
+        f"selected={int(mask_g.sum())} oracle={int(ref['mask'][0].sum())} band={band}")
+    assert int(mask_g.sum()) > 0
