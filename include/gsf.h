@@ -156,8 +156,9 @@ gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const fl
 /* ---- The whole path over a batch of cubes and a filter bank ---- */
 
 /* Bytes of device workspace gsf_find needs for this batch: one slot per
- * concurrently processed cube (min(ncubes, 16)), each sized for the batch's
- * largest array (about 6 of its FP32 cubes).  Pure host. */
+ * concurrently processed cube, each sized for the batch's largest array
+ * (about 6 of its FP32 cubes); min(ncubes, 32) slots, fewer when that many
+ * would exceed 64 GiB (at least one).  Pure host. */
 gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
                                    int32_t nfilt, gsf_box b, size_t *bytes);
 
@@ -172,7 +173,7 @@ gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const 
  * type, the window sums stay FP32.  ws: at least gsf_find_workspace_size
  * bytes (sized for FP32, enough for every storage type).
  * Cubes are independent: with more than one cube the call forks `stream`
- * into up to 16 library-owned streams (created on first use per device, kept
+ * into up to 32 library-owned streams (created on first use per device, kept
  * until the process ends, default priority), gives each its own slice of ws,
  * runs the largest cubes first on the least loaded stream, and makes
  * `stream` wait for all of them before returning (also after an error), so

@@ -402,16 +402,28 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
 // [T1][F scratch][statistics workspace]; a single cube runs on the caller's
 // stream.
 // Measured on the 96-sub-cube batch: 4 slots 85 ms per call, 8 slots 78 ms,
-// 16 slots 75 ms (each slot holds a workspace for the largest cube).
-constexpr int kSlots = 16;
+// 16 slots 75 ms; with the later kernels 16 slots 71.0 ms, 24 69.7 ms, 32
+// 67.8 ms, 48 67.9 ms, 64 68.1 ms.  Each slot holds a workspace for the
+// largest cube, so the slot count is also capped at what fits kSlotBudget
+// bytes of workspace (at least one slot).
+constexpr int kSlots = 32;
+constexpr size_t kSlotBudget = (size_t)64 << 30;
 
-int find_slots(int32_t ncubes) { return ncubes < kSlots ? ncubes : kSlots; }
+size_t slot_ws(gsf_dims largest);
+
+int find_slots(int32_t ncubes, gsf_dims largest)
+{
+    int n = ncubes < kSlots ? ncubes : kSlots;
+    const size_t fit = kSlotBudget / slot_ws(largest);
+    if ((size_t)n > fit) n = fit > 0 ? (int)fit : 1;
+    return n;
+}
 
 size_t slot_ws(gsf_dims largest) { return 2 * cube_bytes(largest) + stats_ws(largest); }
 
 size_t find_ws(gsf_dims largest, int32_t ncubes)
 {
-    return (size_t)find_slots(ncubes) * slot_ws(largest);
+    return (size_t)find_slots(ncubes, largest) * slot_ws(largest);
 }
 
 // Library streams and fork/join events of one device, created on first use
@@ -501,7 +513,7 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
         }
     }
     // Largest cubes first, each to the slot with the least work so far.
-    const int nslots = find_slots(ncubes);
+    const int nslots = find_slots(ncubes, largest);
     std::vector<int32_t> order((size_t)ncubes);
     for (int32_t c = 0; c < ncubes; ++c) order[(size_t)c] = c;
     auto vox = [&](int32_t c) { return cubes[c].dims.nx * cubes[c].dims.ny * cubes[c].dims.nz; };

@@ -75,6 +75,32 @@ def test_workspace_sizes(L):
     assert n3.value >= 5 * 100 * 10 * 300 * 4
 
 
+def _find_ws(L, dims, ncubes):
+    cubes = (B.Cube * ncubes)()
+    for c in cubes:
+        c.data = 256
+        c.dims = dims
+    filt = (B.Filter * 1)(B.Filter(1, 1, 3))
+    n = ctypes.c_size_t(0)
+    assert L.gsf_find_workspace_size(cubes, ncubes, filt, 1, B.Box(8, 8, 8), ctypes.byref(n)) == 0
+    return n.value
+
+
+def test_find_workspace_slots(L):
+    # one workspace slot per concurrently processed cube, at most 32 of them
+    small = B.Dims(64, 64, 128)
+    one = _find_ws(L, small, 1)
+    assert _find_ws(L, small, 5) == 5 * one
+    assert _find_ws(L, small, 32) == 32 * one
+    assert _find_ws(L, small, 40) == 32 * one
+    # and no more slots than fit 64 GiB (at least one)
+    big = B.Dims(1024, 1024, 1024)
+    slot = _find_ws(L, big, 1)
+    assert _find_ws(L, big, 10) == max(1, (64 << 30) // slot) * slot
+    huge = B.Dims(2048, 2048, 2048)
+    assert _find_ws(L, huge, 3) == _find_ws(L, huge, 1)
+
+
 @pytest.mark.parametrize("dims,f,code", [
     (B.Dims(0, 4, 4), B.Filter(1, 1, 3), B.GSF_ERR_INVALID_ARG),
     (B.Dims(4, 4, -1), B.Filter(1, 1, 3), B.GSF_ERR_INVALID_ARG),
