@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,11 +37,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_04941_amd", "csrc", n)
                             "gsf_device.h", "gsf_internal.h", "gsf_api.cpp")]
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines: what the compiler sees
+    (the sources hold no comment markers inside string literals)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line.strip())
+
+
 def kernel_source_sha() -> str:
+    """Hash of the kernel and dispatch sources, comments excluded: a
+    counter summary stays valid across comment edits, not across code edits."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

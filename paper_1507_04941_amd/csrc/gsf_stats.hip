@@ -266,9 +266,11 @@ constexpr int kYzRows = 8;
 // each BZ-lane group gives at lane i the tail of segment j from BZ-1-q, a
 // scan of the B values gives heads of segment j+1, and lane i finishes output
 // column j*BZ + BZ-1-q by adding the head of length BZ-1-q fetched from lane
-// j*BZ + BZ-2-q.  A scan only adds same-window partial sums, so each window
-// sum is accurate relative to itself.  Every column is walked once, plus one
-// strip of halo per block.
+// j*BZ + BZ-2-q (for BZ = 32 and 64 the pair form below does the same with
+// two adjacent columns per lane).  A scan only adds same-window partial
+// sums, so each window sum is accurate relative to itself.  Every column is
+// walked once, plus one strip of halo per block.  The sums are written as
+// interleaved {G1, G2} pairs.
 //
 // Measured on the 512x512x1024 cube (64^3 box): 9 waves (one block per CU)
 // 0.63 ms; 5 waves (a quarter of the walk is halo) 0.70 ms; 16 rows per
