@@ -66,3 +66,9 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_source_hash_ignores_comments_only():
+    code = "int a = 1;  // one\n/* block\n   comment */\nint b = 2;\n"
+    assert bench._code_only(code) == bench._code_only("int a = 1;\n\nint b = 2;  // two\n")
+    assert bench._code_only(code) != bench._code_only("int a = 1;\nint b = 3;\n")
