@@ -1,10 +1,10 @@
-"""GPU parity at the measured size with binary16 storage: the 512x512x1024
-cube rounded to binary16, the six-filter bank and 64^3 boxes, in the launch
-configuration the benchmark times for its FP16 line (one gsf_find over all
-filters, the cube, the spectral intermediate and F stored in binary16).
-Every voxel of F, the local mean and std and the mask of each filter is
-compared with the FP64 oracle run on the same rounded cube, to the 16-bit
-bounds of the parity helpers."""
+"""GPU parity at the measured size with 16-bit storage: the 512x512x1024
+cube rounded to binary16 or bfloat16, the six-filter bank and 64^3 boxes, in
+the launch configuration the benchmark times for its FP16 and BF16 lines
+(one gsf_find over all filters, the cube, the spectral intermediate and F
+stored in the 16-bit type).  Every voxel of F, the local mean and std and the
+mask of each filter is compared with the FP64 oracle run on the same rounded
+cube, to the 16-bit bounds of the parity helpers."""
 import numpy as np
 import pytest
 import torch
@@ -21,34 +21,38 @@ DEV = "cuda:0"
 W = synth.LARGE
 
 
-@pytest.fixture(scope="module")
-def large16():
-    log(f"full size f16: generating {W.name}")
-    d16 = round16(synth.workload_cube(W), "f16")
-    g = torch.from_numpy(d16).to(DEV).to(torch.float16)
-    log("full size f16: gsf_find with F, mean and std")
+TORCH = {"f16": torch.float16, "bf16": torch.bfloat16}
+
+
+@pytest.fixture(scope="module", params=["f16", "bf16"])
+def large16(request):
+    name = request.param
+    log(f"full size {name}: generating {W.name}")
+    d16 = round16(synth.workload_cube(W), name)
+    g = torch.from_numpy(d16).to(DEV).to(TORCH[name])
+    log(f"full size {name}: gsf_find with F, mean and std")
     out = B.find(g, W.filters, W.box, W.k, want_F=True, want_stats=True)
     torch.cuda.synchronize()
-    yield d16, out
+    yield name, d16, out
     del out, g
     torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("j", range(len(W.filters)))
-def test_every_voxel_matches_oracle_f16(large16, j):
-    d16, out = large16
+def test_every_voxel_matches_oracle_16(large16, j):
+    name, d16, out = large16
     f = W.filters[j]
-    log(f"full size f16 filter {f}: oracle")
+    log(f"full size {name} filter {f}: oracle")
     ref = oracle.find(d16, [f], W.box, W.k, want_F=True, want_stats=True)
     scale = cube_scale(d16)
     Fg = out["F"][0][j].to(torch.float32).cpu().numpy()
-    wf = check_filtered(Fg, ref["F"][0], f, scale, what="F f16", rel=REL16_F["f16"])
+    wf = check_filtered(Fg, ref["F"][0], f, scale, what=f"F {name}", rel=REL16_F[name])
     wm, ws = check_stats(out["mean"][0][j].cpu().numpy(), out["std"][0][j].cpu().numpy(),
-                         ref["mean"][0], ref["std"][0], sigma_f(f) * scale, what="stats f16",
-                         rel=REL16["f16"])
+                         ref["mean"][0], ref["std"][0], sigma_f(f) * scale, what=f"stats {name}",
+                         rel=REL16[name])
     mask_g = B.unpack_mask(out["mask"][0][j], d16.shape)
     band = check_mask(mask_g, ref["F"][0], ref["mean"][0], ref["std"][0], W.k, f, scale,
-                      what="mask f16", rel=REL16["f16"], rel_f=REL16_F["f16"])
+                      what=f"mask {name}", rel=REL16[name], rel_f=REL16_F[name])
     log(f"  F/bound={wf:.3g} mean/bound={wm:.3g} std/bound={ws:.3g} "
         f"selected={int(mask_g.sum())} oracle={int(ref['mask'][0].sum())} band={band}")
     assert int(mask_g.sum()) > 0
