@@ -409,7 +409,8 @@ const ZFn *ztab_of(std::integer_sequence<int, R...>)
 // Rows per lane, measured on the 512x512x1024 cube.  R = 12: two rows (115
 // VGPRs, two 8-wave blocks per CU) 0.70 ms, three rows (one block per CU)
 // 0.89 ms, one row (3.5x halo rows per output row) 0.87 ms.  R = 6: two rows
-// 0.49 ms, three 0.52 ms, four 0.51 ms.  R = 3: four rows 0.43 ms.
+// 0.49 ms, three 0.52 ms, four 0.51 ms.  R = 3: four rows 0.44 ms, two
+// 0.45 ms, three 0.49 ms.
 template <int R>
 constexpr int yx_rows() { return R <= 3 ? 4 : R <= 12 ? 2 : 1; }
 
