@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_04941_amd", "csrc", n)
                   for n in ("gsf_kernels.hip", "gsf_filter.hip", "gsf_stats.hip",
-                            "gsf_device.h", "gsf_internal.h", "gsf_api.cpp")]
+                            "gsf_merged.h", "gsf_device.h", "gsf_internal.h", "gsf_api.cpp")]
 
 
 def _code_only(text: str) -> str:
@@ -55,12 +55,31 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, V: int) -> float | None:
-    """Bytes one launch of `kernel` must move for a V-voxel FP32 cube: each
-    input read once and each output written once (masks are V/8 bytes)."""
+# Algorithmic bytes per voxel-filter, the method's minimum: read the cube
+# once and write one mask bit (4 + 1/8 bytes with FP32 storage, 2 + 1/8 with
+# 16-bit storage).  A kernel's algorithmic bytes per launch are this figure
+# times the voxel-filters the launch serves; the whole step serves
+# voxels x filters.
+ALG_BYTES_PER_VF = {"f32": 4.125, "f16": 2.125, "bf16": 2.125}
+
+
+def one_read_bytes_per_vf(storage: str, nfilt: int) -> float:
+    """Bytes per voxel-filter if one read of the cube fed every filter and
+    each filter wrote its mask bit: (element + nfilt/8) / nfilt."""
+    elem = 4.0 if storage == "f32" else 2.0
+    return (elem + nfilt / 8.0) / nfilt
+
+
+def kernel_io_bytes(kernel: str, V: int) -> float | None:
+    """Bytes one launch of `kernel` reads and writes for a V-voxel FP32 cube
+    in this design (each of its inputs read once, each output written once;
+    masks are V/8 bytes).  This counts the design's own intermediates (the
+    spectral intermediate, F, the window-sum pairs), unlike ALG_BYTES_PER_VF."""
     table = {
         "k_zpass_r": 8.0 * V,          # read d, write T1
         "k_yx_r": 8.0 * V,             # read T1, write F
+        "k_yx3_r": 16.0 * V,           # read T1, write three F
+        "k_yx2_r": 12.0 * V,           # read T1, write two F
         "k_zpass": 8.0 * V,
         "k_strided_pass": 8.0 * V,     # read T, write T'
         "k_partial_sums": 4.0 * V,     # read F
@@ -74,6 +93,32 @@ def algorithmic_bytes(kernel: str, V: int) -> float | None:
     }
     kernel = kernel.split("<")[0]
     return table.get(kernel)
+
+
+def roofline_for(kern: dict, V: int, nfilt: int, steps: int, storage: str,
+                 total_ms: float) -> dict | None:
+    """The dominant kernel's roofline at the method's algorithmic bytes:
+    ALG_BYTES_PER_VF x the voxel-filters one launch serves (voxels x filters
+    x steps / its launches) over its mean launch duration."""
+    if not kern:
+        return None
+    dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    n, ms = kern[dom]
+    avg_ms = ms / n
+    units = V * nfilt * steps / n
+    alg = ALG_BYTES_PER_VF[storage] * units
+    ach = alg / (avg_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom,
+           "avg_launch_ms": round(avg_ms, 4), "voxel_filters_per_launch": units,
+           "algorithmic_bytes_per_launch": alg,
+           "share_of_profiled_step": round(ms / total_ms, 3)}
+    io = kernel_io_bytes(dom, V) if storage == "f32" else None
+    if io is not None:
+        io_gbs = io / (avg_ms * 1e-3) / 1e9
+        out["kernel_io"] = {"bytes_per_launch": io, "achieved": round(io_gbs, 1),
+                            "frac": round(io_gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def traffic_file(kernel: str, workload: str) -> str:
@@ -102,14 +147,29 @@ def read_traffic(kernel: str, workload: str, sha: str):
         return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, d, target_s: float):
-    """The FP64 oracle on the host cores over a bounded x-slab of the cube."""
+    """The FP64 oracle on the host cores over bounded x-slabs of the cube:
+    with all the threads it uses by default (about target_s of work), then
+    with one thread (about target_s / 2)."""
     import numpy as np
 
     import oracle
     oracle._load()
     threads = oracle.get_threads()
     nx = w.shape[0]
+    plane = w.shape[1] * w.shape[2]
 
     def run(n):
         sub = np.ascontiguousarray(d[:n])
@@ -117,20 +177,34 @@ def cpu_baseline(w, d, target_s: float):
         oracle.find(sub, w.filters, w.box, w.k)
         return time.perf_counter() - t0
 
-    n = min(4, nx)
-    t = run(n)
-    if t < target_s / 3 and n < nx:
-        n = int(min(nx, max(n + 1, n * target_s / max(t, 1e-3))))
+    def leg(target):
+        n = min(2, nx)
         t = run(n)
-    vox = n * w.shape[1] * w.shape[2]
-    return {
-        "value": vox * len(w.filters) / t / 1e9,
+        if t < target / 3 and n < nx:
+            n = int(min(nx, max(n + 1, n * target / max(t, 1e-3))))
+            t = run(n)
+        return n, t
+
+    n, t = leg(target_s)
+    out = {
+        "value": n * plane * len(w.filters) / t / 1e9,
         "unit": "GVoxel-filters/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"x-slab {n}x{w.shape[1]}x{w.shape[2]} of the same cube, all "
                    f"{len(w.filters)} filters + stats + threshold, FP64, {t:.1f} s wall"),
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
     }
+    try:
+        oracle.set_threads(1)
+        n1, t1 = leg(target_s / 2)
+    finally:
+        oracle.set_threads(threads)
+    out["one_thread"] = {
+        "value": n1 * plane * len(w.filters) / t1 / 1e9,
+        "sample": f"x-slab {n1}x{w.shape[1]}x{w.shape[2]}, one thread, {t1:.1f} s wall"}
+    return out
 
 
 def copy_bandwidth(device, nbytes: int = 1 << 30, reps: int = 5) -> float:
@@ -164,19 +238,135 @@ def copy_calibration(device, nbytes: int = 1 << 30, reps: int = 3) -> None:
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def timed_ms(run, steps: int) -> float:
+    """Milliseconds per call of run() over `steps` calls on the current stream,
+    bracketed by device synchronisations (library profiling off)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def profiled(run, steps: int, B) -> tuple[dict, float]:
+    """Per-kernel launches and summed milliseconds over `steps` calls, each
+    library kernel bracketed by hipEvents on its own stream (a separate pass
+    from the headline timing), and the pass's wall time in ms."""
+    import torch
+    B.profile_reset()
+    B.profile_enable(True)
+    try:
+        ms = timed_ms(run, steps) * steps
+    finally:
+        B.profile_enable(False)
+    kern = B.profile_collect()
+    B.profile_reset()
+    torch.cuda.synchronize()
+    return kern, ms
+
+
+def kernel_table(kern: dict, V: int) -> dict:
+    out = {}
+    for k, (n, ms) in kern.items():
+        out[k] = {"launches": n, "avg_ms": round(ms / n, 5), "total_ms": round(ms, 4)}
+        io = kernel_io_bytes(k, V)
+        if io is not None:
+            out[k]["io_gbs"] = round(io / (ms / n * 1e-3) / 1e9, 1)
+    return out
+
+
+def noise_sigma_f(f, truncate: float) -> float:
+    """sqrt(sum of the squared 3-D taps): the filtered-noise sigma for unit
+    input noise (the taps are the sampled unit-sum Gaussians)."""
+    import math
+
+    def sumsq(sigma):
+        r = int(math.ceil(truncate * sigma))
+        g = [math.exp(-(o * o) / (2.0 * sigma * sigma)) for o in range(-r, r + 1)]
+        t = sum(g)
+        return sum((v / t) ** 2 for v in g)
+
+    return math.sqrt(sumsq(f[0]) ** 2 * sumsq(f[1]))
+
+
+def unpack_bits(words, shape):
+    """Packed mask words (nx, ny, W) on the device -> bool tensor (nx, ny, nz)."""
+    import torch
+    nx, ny, nz = (int(v) for v in shape)
+    b = words.contiguous().view(torch.uint8).reshape(nx, ny, -1, 1)
+    bits = (b >> torch.arange(8, device=words.device, dtype=torch.uint8)) & 1
+    return bits.reshape(nx, ny, -1)[:, :, :nz].bool()
+
+
+def errors16(B, cube32, name, w) -> dict:
+    """Errors of the 16-bit-storage path against the FP32 path on the same
+    cube (the FP32 path is held to the FP64 oracle within 1e-5 of the local
+    std by the parity tests), per filter, in units of the local std (the FP32
+    path's std, floored at the filtered-noise sigma): F (also relative to
+    max(|F|, local std)), mean, std, and the masks' differences outside the
+    band a 1e-3-of-local-std error on mean and std (and 1e-3 relative on F)
+    could move a voxel across."""
+    import torch
+    dt = {"f16": torch.float16, "bf16": torch.bfloat16}[name]
+    rms = float(torch.sqrt(torch.mean(cube32.double() ** 2)))
+    c16 = cube32.to(dt)
+    per = []
+    for f in w.filters:
+        ref = B.find(cube32, [f], w.box, w.k, want_F=True, want_stats=True)
+        out = B.find(c16, [f], w.box, w.k, want_F=True, want_stats=True)
+        torch.cuda.synchronize()
+        F32 = ref["F"][0][0].double()
+        m32 = ref["mean"][0][0].double()
+        s32 = ref["std"][0][0].double()
+        unit = torch.clamp(s32, min=noise_sigma_f(f, w.truncate) * rms)
+        dF = (out["F"][0][0].double() - F32).abs()
+        e_f = float((dF / unit).max())
+        e_fr = float((dF / torch.maximum(F32.abs(), unit)).max())
+        del dF
+        e_m = float(((out["mean"][0][0].double() - m32).abs() / unit).max())
+        e_s = float(((out["std"][0][0].double() - s32).abs() / unit).max())
+        thr = m32 + w.k * s32
+        band = (F32 - thr).abs() <= 1e-3 * (torch.maximum(F32.abs(), unit) + unit + w.k * unit)
+        sel32 = F32 > thr
+        del m32, s32, unit
+        mg = unpack_bits(out["mask"][0][0], F32.shape)
+        diff = mg != sel32
+        per.append({"filter": list(f),
+                    "F_max_local_std": round(e_f, 6),
+                    "F_max_rel": round(e_fr, 6),
+                    "mean_max_local_std": round(e_m, 6),
+                    "std_max_local_std": round(e_s, 6),
+                    "mask_diffs": int(diff.sum()),
+                    "mask_diffs_outside_band": int((diff & ~band).sum()),
+                    "band_voxels": int(band.sum()),
+                    "selected": int(mg.sum())})
+        del F32, thr, band, sel32, mg, diff, ref, out
+        torch.cuda.empty_cache()
+    del c16
+    torch.cuda.empty_cache()
+    return {"against": "the FP32 path on the same cube", "unit": "local std", "filters": per}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["large", "small"])
-    ap.add_argument("--cpu-seconds", type=float, default=20.0,
-                    help="target wall time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="target wall time of the oracle sample with all threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-storage16", action="store_true",
                     help="skip the FP16/BF16-storage timings")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the 16-bit error figures")
     ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batch of 96 halo sub-cubes")
+                    help="skip the batch of 96 halo sub-cubes and the weighted form")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the serving run (Poisson, 200/s); 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -201,6 +391,7 @@ def main() -> int:
     if args.copy_calibration:
         copy_calibration(dev)
         return 0
+    B.init()
 
     w = synth.LARGE if args.workload == "large" else synth.SMALL
     t0 = time.perf_counter()
@@ -209,55 +400,42 @@ def main() -> int:
     cube = torch.from_numpy(d).to(dev)
     plan = B.FindPlan([cube], w.filters, w.box, w.k)
     V = w.voxels
+    nf = len(w.filters)
     for _ in range(args.warmup):
         plan.run()
     torch.cuda.synchronize()
     print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
-    B.profile_reset()
-    B.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        plan.run()
-    e1.record()
-    torch.cuda.synchronize()
-    B.profile_enable(False)
-    total_ms = e0.elapsed_time(e1)
-    kern = B.profile_collect()
-    print(f"# timed {args.steps} steps: {total_ms:.2f} ms", file=sys.stderr, flush=True)
+    # headline: library profiling off
+    ms_per_step = timed_ms(plan.run, args.steps)
+    value = V * nf / (ms_per_step * 1e-3) / 1e9
+    print(f"# timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    ms_per_step = total_ms / args.steps
-    value = V * len(w.filters) / (ms_per_step * 1e-3) / 1e9
-    kernels = {k: {"launches": n, "avg_ms": ms / n, "total_ms": ms} for k, (n, ms) in kern.items()}
-    dom = max(kern.items(), key=lambda kv: kv[1][1])[0] if kern else None
-    roof = None
-    if dom is not None:
-        n, ms = kern[dom]
-        avg_ms = ms / n
-        alg = algorithmic_bytes(dom, V)
+    # per-kernel durations in a second pass, with hipEvents around each launch
+    kern, prof_ms = profiled(plan.run, args.steps, B)
+    roof = roofline_for(kern, V, nf, args.steps, "f32", prof_ms)
+    if roof is not None:
         sha = kernel_source_sha()
-        traffic = read_traffic(dom, w.name, sha)
-        if alg is not None:
-            ach = alg / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
-                    "algorithmic_bytes_per_launch": alg, "share_of_step": round(ms / total_ms, 3)}
-            if traffic is not None:
-                roof["traffic_over_algorithmic"] = round(traffic / alg, 4)
-            copy_gbs = copy_bandwidth(dev)
-            roof["copy_gbs"] = round(copy_gbs, 1)
-            roof["frac_of_copy"] = round(ach / copy_gbs, 4)
-            print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    for k, (n, ms) in kern.items():
-        a = algorithmic_bytes(k, V)
-        if a is not None:
-            kernels[k]["algorithmic_gbs"] = round(a / (ms / n * 1e-3) / 1e9, 1)
+        roof["traffic"] = read_traffic(roof["kernel"], w.name, sha)
+        if roof["traffic"] is not None:
+            roof["traffic_over_algorithmic"] = round(roof["traffic"] /
+                                                     roof["algorithmic_bytes_per_launch"], 3)
+        step_gbs = ALG_BYTES_PER_VF["f32"] * V * nf / (ms_per_step * 1e-3) / 1e9
+        roof["step"] = {"algorithmic_bytes": ALG_BYTES_PER_VF["f32"] * V * nf,
+                        "achieved": round(step_gbs, 1),
+                        "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+        one = one_read_bytes_per_vf("f32", nf)
+        one_gbs = one * V * nf / (ms_per_step * 1e-3) / 1e9
+        roof["step_one_read"] = {"bytes_per_voxel_filter": round(one, 4),
+                                 "achieved": round(one_gbs, 1),
+                                 "frac": round(one_gbs / HBM_PEAK_GBS, 4)}
+        copy_gbs = copy_bandwidth(dev)
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        print(f"# device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    kernels = kernel_table(kern, V)
 
-    # the same step with the cube, T1 and F stored in 16 bits (window sums FP32)
+    # the same step with the cube and F stored in 16 bits (FP32 spectral
+    # intermediate and window sums)
     storage16 = {}
     if not args.no_storage16:
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
@@ -265,23 +443,23 @@ def main() -> int:
             p16 = B.FindPlan([c16], w.filters, w.box, w.k)
             for _ in range(args.warmup):
                 p16.run()
-            B.profile_reset()
-            B.profile_enable(True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
-                p16.run()
-            e1.record()
-            torch.cuda.synchronize()
-            B.profile_enable(False)
-            t16 = e0.elapsed_time(e1) / args.steps
-            k16 = B.profile_collect()
+            t16 = timed_ms(p16.run, args.steps)
+            k16, p16_ms = profiled(p16.run, args.steps, B)
+            r16 = roofline_for(k16, V, nf, args.steps, name, p16_ms)
+            g16 = ALG_BYTES_PER_VF[name] * V * nf / (t16 * 1e-3) / 1e9
             storage16[name] = {
-                "value": round(V * len(w.filters) / (t16 * 1e-3) / 1e9, 3),
+                "value": round(V * nf / (t16 * 1e-3) / 1e9, 3),
                 "ms_per_step": round(t16, 4),
-                "kernels": {k: {"launches": n, "avg_ms": ms / n} for k, (n, ms) in k16.items()}}
+                "speedup_vs_f32": round(ms_per_step / t16, 3),
+                "roofline": r16,
+                "step_frac": round(g16 / HBM_PEAK_GBS, 4),
+                "kernels": kernel_table(k16, V)}
             print(f"# {name} storage: {t16:.3f} ms/step", file=sys.stderr, flush=True)
             del p16, c16
+            torch.cuda.empty_cache()
+            if not args.no_errors:
+                storage16[name]["errors"] = errors16(B, cube, name, w)
+                print(f"# {name} errors done", file=sys.stderr, flush=True)
 
     # the weighted convolution (Eq. 1) of the same cube, one filter, random weights
     weighted = None
@@ -296,44 +474,52 @@ def main() -> int:
                                                               B.ctypes.byref(B._filter(fw)),
                                                               B.ctypes.byref(n)))
         wsw = torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+
+        def wrun():
+            B.filter3d_weighted(cube, wts, fw, out=outw, ws=wsw)
+
         for _ in range(args.warmup):
-            B.filter3d_weighted(cube, wts, fw, out=outw, ws=wsw)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            B.filter3d_weighted(cube, wts, fw, out=outw, ws=wsw)
-        e1.record()
-        torch.cuda.synchronize()
-        tw = e0.elapsed_time(e1) / args.steps
+            wrun()
+        tw = timed_ms(wrun, args.steps)
         weighted = {"filter": list(fw), "ms_per_call": round(tw, 3),
                     "value": round(V / (tw * 1e-3) / 1e9, 3), "unit": "GVoxel-filters/s"}
         print(f"# weighted: {tw:.3f} ms per call", file=sys.stderr, flush=True)
         del wts, outw, wsw
+        torch.cuda.empty_cache()
 
-    # the batched form: 96 uneven sub-cubes with halos in one gsf_find call
+    # the batched form: 96 uneven sub-cubes with halos in one gsf_find call,
+    # eager and as one captured HIP graph, FP32 and FP16 storage
     batch = None
     if not args.no_batch:
         bw = synth.BATCH
         t0 = time.perf_counter()
-        cubes = [torch.from_numpy(synth.batch_cube(bw, i)).to(dev) for i in range(bw.n_cubes)]
+        host = [synth.batch_cube(bw, i) for i in range(bw.n_cubes)]
         print(f"# generated {bw.name} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
-        pb = B.FindPlan(cubes, bw.filters, bw.box, bw.k, halos=bw.halo)
-        for _ in range(args.warmup):
-            pb.run()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            pb.run()
-        e1.record()
-        torch.cuda.synchronize()
-        tb = e0.elapsed_time(e1) / args.steps
         core_vox = sum(a * b_ * c for a, b_, c in synth.batch_cores(bw))
         batch = {"workload": bw.name, "cubes": bw.n_cubes, "core_voxels": core_vox,
-                 "value": round(core_vox * len(bw.filters) / (tb * 1e-3) / 1e9, 3),
-                 "unit": "GVoxel-filters/s", "ms_per_call": round(tb, 3)}
-        print(f"# batch: {tb:.2f} ms per call", file=sys.stderr, flush=True)
-        del pb, cubes
+                 "unit": "GVoxel-filters/s"}
+        for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
+            cubes = [torch.from_numpy(h).to(dev).to(dt) for h in host]
+            pb = B.FindPlan(cubes, bw.filters, bw.box, bw.k, halos=bw.halo)
+            for _ in range(args.warmup):
+                pb.run()
+            tb = timed_ms(pb.run, args.steps)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                pb.run()
+            for _ in range(args.warmup):
+                graph.replay()
+            tg = timed_ms(graph.replay, args.steps)
+            batch[name] = {"value": round(core_vox * nf / (tb * 1e-3) / 1e9, 3),
+                           "ms_per_call": round(tb, 3),
+                           "graph_value": round(core_vox * nf / (tg * 1e-3) / 1e9, 3),
+                           "graph_ms_per_replay": round(tg, 3)}
+            print(f"# batch {name}: {tb:.2f} ms per call, {tg:.2f} ms per graph replay",
+                  file=sys.stderr, flush=True)
+            del graph, pb, cubes
+            torch.cuda.empty_cache()
+        del host
 
     # the serving form: Poisson arrivals of lognormal-volume sub-cubes,
     # four streams, 200 GB budget, device-resident F/mean/std
@@ -347,13 +533,14 @@ def main() -> int:
         for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
             t_arr, shapes = arr.draw(args.serve_requests)
             reqs = [serve.Request(j, float(t_arr[j]),
-                                  serve.device_noise(shapes[j], arr.cube_seed + j, dev, dt))
+                                  serve.device_cube(shapes[j], arr.cube_seed + j, dev, dt))
                     for j in range(args.serve_requests)]
             big = max(reqs, key=lambda r: r.voxels).cube.shape
             srv = serve.Server(w.filters, w.box, w.k, lanes=4, max_shape=big, device=dev, dtype=dt)
             srv.run(reqs)                                   # warm the allocator
             st = srv.run(reqs)
             serving[name] = {k: round(v, 3) for k, v in st.items() if isinstance(v, float)}
+            serving[name]["rejected"] = st["rejected"]
             print(f"# serving {name}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms",
                   file=sys.stderr, flush=True)
             del reqs, srv

@@ -107,9 +107,8 @@ gsf_status gsf_filter3d_workspace_size(gsf_dims d, const gsf_filter *f, size_t *
  * (GSF_F32, GSF_F16 or GSF_BF16; otherwise GSF_ERR_UNSUPPORTED); they must
  * not overlap.  ws: at least gsf_filter3d_workspace_size bytes (may be NULL
  * when that figure is 0).  FP32 arithmetic, taps summed in the fixed order
- * -r..r per axis; with 16-bit storage the spectral-pass intermediate is
- * stored in that type too, and every stored value is rounded to nearest
- * even. */
+ * -r..r per axis; the spectral-pass intermediate is FP32 (in ws) whatever
+ * the storage type, and a 16-bit output is rounded to nearest even. */
 gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_filter *f,
                         void *out, gsf_dtype out_t, void *ws, size_t ws_bytes, void *stream);
 
@@ -153,12 +152,25 @@ gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b,
 gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const float *stdev,
                          gsf_dims d, double k, uint64_t *mask, void *stream);
 
+/* ---- Library set-up ---- */
+
+/* Create the library's per-device state on the current device, once: the
+ * streams a multi-cube gsf_find forks onto.  Optional (they are otherwise
+ * created by the first call that needs them), but required before a graph
+ * capture whose first such call is captured: streams are not created inside a
+ * capture (gsf_find then returns GSF_ERR_UNSUPPORTED).  Idempotent;
+ * GSF_ERR_DEVICE if a HIP call fails. */
+gsf_status gsf_init(void);
+
 /* ---- The whole path over a batch of cubes and a filter bank ---- */
 
 /* Bytes of device workspace gsf_find needs for this batch: one slot per
- * concurrently processed cube, each sized for the batch's largest array
- * (about 6 of its FP32 cubes); min(ncubes, 32) slots, fewer when that many
- * would exceed 64 GiB (at least one).  Pure host. */
+ * concurrently processed cube, each sized for the batch's largest array: the
+ * FP32 spectral intermediate, one FP32-sized F per filter sharing it (at most
+ * 3), two (four if a cube needs the generic statistics path) FP32 cubes of
+ * window sums, plus about 0.5 MiB per F; min(ncubes, 32) slots, fewer when
+ * that many would exceed 64 GiB (at least one).  Pure host; independent of
+ * the tuning. */
 gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
                                    int32_t nfilt, gsf_box b, size_t *bytes);
 
@@ -169,12 +181,14 @@ gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const 
  * F_out, mean_out, std_out: NULL, or arrays of ncubes*nfilt device pointers
  * (each may be NULL) receiving the filtered cube (in the cube's dtype), local
  * mean and local std (floats).  A cube may be stored as GSF_F32, GSF_F16 or
- * GSF_BF16; its spectral-pass intermediate and F are then stored in that
- * type, the window sums stay FP32.  ws: at least gsf_find_workspace_size
- * bytes (sized for FP32, enough for every storage type).
+ * GSF_BF16; F is then stored in that type (the mask is taken from the
+ * stored F), while the spectral-pass intermediate and the window sums stay
+ * FP32.  ws: at least gsf_find_workspace_size bytes (sized for FP32, enough
+ * for every storage type).
  * Cubes are independent: with more than one cube the call forks `stream`
- * into up to 32 library-owned streams (created on first use per device, kept
- * until the process ends, default priority), gives each its own slice of ws,
+ * into up to 32 library-owned streams (created by gsf_init or on first use
+ * per device outside a capture, kept until the process ends, default
+ * priority), gives each its own slice of ws,
  * runs the largest cubes first on the least loaded stream, and makes
  * `stream` wait for all of them before returning (also after an error), so
  * the results are ordered on `stream` as for one cube.  Such calls from
@@ -184,6 +198,42 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                     gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
                     float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
                     void *stream);
+
+/* ---- Launch tuning ---- */
+
+/* Launch configuration of the kernels that have several compiled shapes.
+ * Every setting gives results within the parity bounds; the filtered values F
+ * are bit-identical across settings, the statistics may differ in rounding
+ * (a different x split changes the order of the shift's partial sums). */
+typedef struct gsf_tuning {
+    int32_t merge_sweeps;  /* 1 (default): the filters of a group that shares one
+                              spectral pass (equal sigma_z) get one merged spatial
+                              sweep where a form is compiled (spatial radii
+                              {3,6,12}, {3,6}, {3,12}, {6,12}); 0: one sweep each */
+    int32_t merged_shape;  /* merged-sweep block: 0 (default) 1 row per lane x 8
+                              waves, 1: 2 rows x 8 waves, 2: 1 row x 16 waves */
+    int32_t sweep_blocks;  /* blocks a spatial sweep aims for before it splits x
+                              into chunks, 64..65536 (default 512) */
+    int32_t yz_waves;      /* waves per block of the yz window-sum kernel: 0
+                              (default: fewest columns walked for the depth), 3, 5
+                              or 9 */
+} gsf_tuning;
+
+/* Size class of a cube core: floor(log2(nx*ny*nz)), 0..40; -1 if invalid. */
+int32_t gsf_size_class(gsf_dims core);
+
+/* Set the tuning used for cores of size class `size_class` (-1: every class)
+ * stored as `dtype`, by every later call of this process (gsf_filter3d,
+ * gsf_filter3d_weighted, gsf_local_stats, gsf_find).  The
+ * table is process-wide; calls enqueued concurrently with a change see the
+ * old or the new entry.  GSF_ERR_INVALID_ARG for values out of range. */
+gsf_status gsf_tuning_set(int32_t size_class, gsf_dtype dtype, const gsf_tuning *cfg);
+
+/* The entry of size class `size_class` (0..40) and `dtype`. */
+gsf_status gsf_tuning_get(int32_t size_class, gsf_dtype dtype, gsf_tuning *cfg);
+
+/* Every entry back to the defaults. */
+gsf_status gsf_tuning_reset(void);
 
 /* ---- Kernel timing (measurement aid) ---- */
 

@@ -43,6 +43,11 @@ class Cube(ctypes.Structure):
                 ("halo", ctypes.c_int32 * 3)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("merge_sweeps", ctypes.c_int32), ("merged_shape", ctypes.c_int32),
+                ("sweep_blocks", ctypes.c_int32), ("yz_waves", ctypes.c_int32)]
+
+
 class GsfError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"gsf status {status}: {detail}")
@@ -71,6 +76,11 @@ SIGNATURES = [
     ("gsf_find", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter), ctypes.c_int32,
                        Box, ctypes.c_double, ctypes.POINTER(_P), ctypes.POINTER(_P),
                        ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    ("gsf_init", _ST, []),
+    ("gsf_size_class", ctypes.c_int32, [Dims]),
+    ("gsf_tuning_set", _ST, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(Tuning)]),
+    ("gsf_tuning_get", _ST, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(Tuning)]),
+    ("gsf_tuning_reset", _ST, []),
     ("gsf_profile_enable", _ST, [ctypes.c_int]),
     ("gsf_profile_reset", _ST, []),
     ("gsf_profile_collect", ctypes.c_int32, []),
@@ -329,6 +339,34 @@ class FindPlan:
         _check(lib().gsf_find(self._carr, len(self.cubes), self._farr, len(self.filters), self._box,
                               self.k, self._m, self._F, self._mu, self._sd, self.ws.data_ptr(),
                               self.ws.numel(), s))
+
+
+def init() -> None:
+    """gsf_init: the library's per-device streams, made outside any graph
+    capture."""
+    _check(lib().gsf_init())
+
+
+def size_class(core_shape) -> int:
+    """floor(log2(voxels)) of a core: the key of the library's tuning table."""
+    return int(lib().gsf_size_class(_dims(core_shape)))
+
+
+def tuning_set(cfg: dict, size_class: int = -1, dtype=torch.float32) -> None:
+    """Install a tuning entry (keys of gsf_tuning) for a size class (-1: all)."""
+    t = Tuning(int(cfg.get("merge_sweeps", 1)), int(cfg.get("merged_shape", 0)),
+               int(cfg.get("sweep_blocks", 512)), int(cfg.get("yz_waves", 0)))
+    _check(lib().gsf_tuning_set(int(size_class), _DTYPES[dtype], ctypes.byref(t)))
+
+
+def tuning_get(size_class: int, dtype=torch.float32) -> dict:
+    t = Tuning()
+    _check(lib().gsf_tuning_get(int(size_class), _DTYPES[dtype], ctypes.byref(t)))
+    return {k: int(getattr(t, k)) for k, _ in Tuning._fields_}
+
+
+def tuning_reset() -> None:
+    _check(lib().gsf_tuning_reset())
 
 
 def profile_enable(on: bool = True) -> None:

@@ -2,7 +2,8 @@
 
 The library is the C ABI of include/gsf.h: host dispatch (gsf_api.cpp,
 gsf_prof.cpp) plus the HIP kernels (gsf_kernels.hip, gsf_filter.hip,
-gsf_stats.hip).  Packed FP32 instructions are disabled for every device
+gsf_stats.hip, and the merged spatial sweeps of gsf_merged.h instantiated
+per storage type in gsf_merged_*.hip).  Packed FP32 instructions are disabled for every device
 function (-packed-fp32-ops).  Objects go to _build/ (not tracked).
 """
 from __future__ import annotations
@@ -14,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsf.so")
-SOURCES = ["gsf_api.cpp", "gsf_prof.cpp", "gsf_kernels.hip", "gsf_filter.hip", "gsf_stats.hip"]
+SOURCES = ["gsf_api.cpp", "gsf_prof.cpp", "gsf_kernels.hip", "gsf_filter.hip", "gsf_stats.hip",
+           "gsf_merged_f32.hip", "gsf_merged_f16.hip", "gsf_merged_bf16.hip"]
 ARCH = "gfx950"
 
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "gsf_internal.h"
+#include "gsf_merged.h"
 
 namespace {
 
@@ -131,28 +132,42 @@ gsf::Box to_box(gsf_box b) { return gsf::Box{b.bx, b.by, b.bz}; }
 
 size_t cube_bytes(gsf_dims d) { return align_up((size_t)(d.nx * d.ny * d.nz) * sizeof(float)); }
 
-// Workspace pieces shared by the statistics schedule: four scratch cubes,
-// the per-block partial sums of the shift and the shift itself.
-size_t stats_ws(gsf_dims d)
+// Scratch cubes the statistics need: the interleaved window-sum pairs (two
+// cubes of floats) where the fast kernels apply, four cubes on the generic
+// path.
+int stats_cubes(gsf_box b, gsf_dims d)
 {
-    return 4 * cube_bytes(d) + align_up(gsf::kMaxPartials * sizeof(double)) +
-           align_up(sizeof(double));
+    return gsf::stats_fast_path(to_box(b), to_dims(d)) ? 2 : 4;
 }
 
+// The per-block partial sums of n shifts and the n shifts themselves.
+size_t shift_bytes(int n)
+{
+    return (size_t)n * align_up(gsf::kMaxPartials * sizeof(double)) +
+           align_up((size_t)n * sizeof(double));
+}
+
+// gsf_local_stats: [statistics cubes][partials][shift].
+size_t stats_ws(gsf_dims d, gsf_box b)
+{
+    return (size_t)stats_cubes(b, d) * cube_bytes(d) + shift_bytes(1);
+}
+
+// Statistics workspace: w1..w4 (w3, w4 null with two cubes); partials of
+// shift i at partials + i * kMaxPartials, shift i at shift[i].
 struct StatsWs {
     float *w1, *w2, *w3, *w4;
     double *partials, *shift;
 };
 
-StatsWs carve_stats(char *p, gsf_dims d)
+StatsWs carve_stats(char *p, gsf_dims d, int ncubes, int nshift)
 {
-    StatsWs w;
+    StatsWs w{};
     const size_t c = cube_bytes(d);
-    w.w1 = (float *)p; p += c;
-    w.w2 = (float *)p; p += c;
-    w.w3 = (float *)p; p += c;
-    w.w4 = (float *)p; p += c;
-    w.partials = (double *)p; p += align_up(gsf::kMaxPartials * sizeof(double));
+    float **cubes[4] = {&w.w1, &w.w2, &w.w3, &w.w4};
+    for (int i = 0; i < ncubes; ++i, p += c) *cubes[i] = (float *)p;
+    w.partials = (double *)p;
+    p += (size_t)nshift * align_up(gsf::kMaxPartials * sizeof(double));
     w.shift = (double *)p;
     return w;
 }
@@ -178,7 +193,47 @@ gsf_status device_status(hipError_t e, const char *what)
     return ok();
 }
 
+// ---- tuning table: one entry per (size class, storage type) ----
+constexpr int kSizeClasses = 41;   // floor(log2(voxels)) of a core, 0 .. 40
+
+thread_local gsf::Tune t_active;
+std::mutex g_tune_mu;
+gsf::Tune g_tune[3][kSizeClasses];
+
+int size_class(gsf_dims d)
+{
+    const int64_t v = d.nx * d.ny * d.nz;
+    int c = 0;
+    while (c + 1 < kSizeClasses && ((int64_t)1 << (c + 1)) <= v) ++c;
+    return c;
+}
+
+gsf::Tune tune_for(gsf_dims core, gsf_dtype t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune[(int)t][size_class(core)];
+}
+
+gsf_status check_tuning(const gsf_tuning *c)
+{
+    if (!c) return fail(GSF_ERR_INVALID_ARG, "tuning pointer is NULL");
+    if (c->merge_sweeps != 0 && c->merge_sweeps != 1)
+        return fail(GSF_ERR_INVALID_ARG, "merge_sweeps must be 0 or 1");
+    if (c->merged_shape < 0 || c->merged_shape >= gsf::kMergedShapes)
+        return fail(GSF_ERR_INVALID_ARG, "merged_shape must be in [0, %d)", gsf::kMergedShapes);
+    if (c->sweep_blocks < 64 || c->sweep_blocks > 65536)
+        return fail(GSF_ERR_INVALID_ARG, "sweep_blocks must be in [64, 65536]");
+    if (c->yz_waves != 0 && c->yz_waves != 3 && c->yz_waves != 5 && c->yz_waves != 9)
+        return fail(GSF_ERR_INVALID_ARG, "yz_waves must be 0, 3, 5 or 9");
+    return GSF_OK;
+}
+
 }  // namespace
+
+namespace gsf {
+const Tune &active_tune() { return t_active; }
+void set_active_tune(const Tune &t) { t_active = t; }
+}  // namespace gsf
 
 extern "C" {
 
@@ -234,11 +289,12 @@ gsf_status gsf_filter3d(const void *in, gsf_dtype in_t, gsf_dims d, const gsf_fi
     const gsf::Taps tz = make_taps(f->sigma_z, f->truncate);
     const gsf::Dims dd = to_dims(d);
     const hipStream_t s = (hipStream_t)stream;
-    // T1 (and the generic path's second scratch cube) are stored in in_t
+    // T1 (and the generic path's second scratch cube) are FP32 for every in_t
     void *T1 = ws;
     void *tmp = (char *)ws + cube_bytes(d);
     const gsf::Store sto = to_store(in_t);
     const gsf::Halo h = gsf::no_halo(dd);
+    gsf::set_active_tune(tune_for(d, in_t));
     hipError_t e = gsf::launch_zpass(in, T1, sto, dd, h, tz, s);
     if (e == hipSuccess) e = gsf::launch_yx(T1, out, tmp, sto, dd, h, txy, nullptr, nullptr, s);
     return device_status(e, "gsf_filter3d launch");
@@ -285,6 +341,7 @@ gsf_status gsf_filter3d_weighted(const void *in, const void *w, gsf_dtype t, gsf
     float *D = (float *)((char *)ws + 2 * c);
     void *tmp = (char *)ws + 3 * c;
     const bool fused = gsf::zpass_fast(tz.r) && gsf::yx_fast(txy.r, dd);
+    gsf::set_active_tune(tune_for(d, t));
     hipError_t e;
     if (fused) {
         e = gsf::launch_zpass_mul_fast((const float *)in, (const float *)w, T1, dd, tz, s);
@@ -311,7 +368,7 @@ gsf_status gsf_local_stats_workspace_size(gsf_dims d, gsf_box b, size_t *bytes)
     gsf_status st;
     if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
     if ((st = check_dims(d)) || (st = check_box(b))) return st;
-    *bytes = stats_ws(d);
+    *bytes = stats_ws(d, b);
     return ok();
 }
 
@@ -327,16 +384,17 @@ gsf_status gsf_local_stats(const void *F, gsf_dtype t, gsf_dims d, gsf_box b, fl
     if (stdev && (st = check_ptr(stdev, 16, "stdev"))) return st;
     const size_t nb = (size_t)(d.nx * d.ny * d.nz) * sizeof(float);
     const size_t fb = (size_t)(d.nx * d.ny * d.nz) * elem_bytes(t);
-    const size_t need = stats_ws(d);
+    const size_t need = stats_ws(d, b);
     if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     if ((st = check_ptr(ws, 16, "ws"))) return st;
     if (overlaps(F, fb, mean, nb) || overlaps(F, fb, stdev, nb) || overlaps(mean, nb, stdev, nb) ||
         overlaps(ws, need, F, fb) || overlaps(ws, need, mean, nb) || overlaps(ws, need, stdev, nb))
         return fail(GSF_ERR_INVALID_ARG, "F, mean, stdev and ws must not overlap");
     const gsf::Dims dd = to_dims(d);
-    const StatsWs w = carve_stats((char *)ws, d);
+    const StatsWs w = carve_stats((char *)ws, d, stats_cubes(b, d), 1);
     const hipStream_t s = (hipStream_t)stream;
     const gsf::Store sto = to_store(t);
+    gsf::set_active_tune(tune_for(d, t));
     hipError_t e = gsf::launch_mean(F, sto, dd, w.partials, w.shift, s);
     if (e == hipSuccess)
         e = gsf::launch_stats(F, sto, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4, mean, stdev,
@@ -398,9 +456,8 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
 }
 
 // Independent cubes of a batch run concurrently on up to kSlots library
-// streams forked from the caller's stream, each with its own workspace slot
-// [T1][F scratch][statistics workspace]; a single cube runs on the caller's
-// stream.
+// streams forked from the caller's stream, each with its own workspace slot;
+// a single cube runs on the caller's stream.
 // Measured on the 96-sub-cube batch: 4 slots 85 ms per call, 8 slots 78 ms,
 // 16 slots 75 ms; with the later kernels 16 slots 71.0 ms, 24 69.7 ms, 32
 // 67.8 ms, 48 67.9 ms, 64 68.1 ms.  Each slot holds a workspace for the
@@ -409,79 +466,109 @@ gsf_status check_batch(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *
 constexpr int kSlots = 32;
 constexpr size_t kSlotBudget = (size_t)64 << 30;
 
-size_t slot_ws(gsf_dims largest);
+// Filters a merged spatial sweep handles together (the compiled forms).
+constexpr int kMaxMerge = 3;
 
-int find_slots(int32_t ncubes, gsf_dims largest)
+// One workspace slot, sized for the batch's largest array:
+// [T1][F x nF][statistics cubes x nS][shift partials x nF][shifts x nF].
+// nF is the largest number of filters that share a spectral pass (at most
+// kMaxMerge: larger groups are swept kMaxMerge at a time); nS is 2, or 4
+// when some cube needs the generic statistics path.
+struct Layout {
+    gsf_dims largest;
+    int nF;
+    int nS;
+};
+
+bool same_group(const gsf_filter &a, const gsf_filter &b)
+{
+    return a.sigma_z == b.sigma_z && a.truncate == b.truncate;
+}
+
+Layout find_layout(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                   gsf_box b, gsf_dims largest)
+{
+    Layout L{largest, 1, 2};
+    for (int32_t g = 0; g < nfilt; ++g) {
+        int n = 0;
+        for (int32_t j = 0; j < nfilt; ++j) n += same_group(f[g], f[j]) ? 1 : 0;
+        L.nF = std::max(L.nF, std::min(n, kMaxMerge));
+    }
+    for (int32_t c = 0; c < ncubes; ++c) {
+        const gsf_dims core{cubes[c].dims.nx - 2 * (int64_t)cubes[c].halo[0],
+                            cubes[c].dims.ny - 2 * (int64_t)cubes[c].halo[1],
+                            cubes[c].dims.nz - 2 * (int64_t)cubes[c].halo[2]};
+        L.nS = std::max(L.nS, stats_cubes(b, core));
+    }
+    return L;
+}
+
+size_t slot_ws(const Layout &L)
+{
+    return (size_t)(1 + L.nF + L.nS) * cube_bytes(L.largest) + shift_bytes(L.nF);
+}
+
+int find_slots(int32_t ncubes, const Layout &L)
 {
     int n = ncubes < kSlots ? ncubes : kSlots;
-    const size_t fit = kSlotBudget / slot_ws(largest);
+    const size_t fit = kSlotBudget / slot_ws(L);
     if ((size_t)n > fit) n = fit > 0 ? (int)fit : 1;
     return n;
 }
 
-size_t slot_ws(gsf_dims largest) { return 2 * cube_bytes(largest) + stats_ws(largest); }
-
-size_t find_ws(gsf_dims largest, int32_t ncubes)
+size_t find_ws(const Layout &L, int32_t ncubes)
 {
-    return (size_t)find_slots(ncubes, largest) * slot_ws(largest);
+    return (size_t)find_slots(ncubes, L) * slot_ws(L);
 }
 
-// Library streams and fork/join events of one device, created on first use
-// and kept until the process ends.  Streams have the default priority.
-struct SlotStreams {
+// Per-device library state, created once per device (gsf_init, or the first
+// call that needs it outside a stream capture) and kept until the process
+// ends: the batch streams with their fork/join events (default priority).
+struct DeviceState {
+    bool streams_ready = false;
     hipStream_t stream[kSlots];
     hipEvent_t fork;
     hipEvent_t join[kSlots];
 };
 
-std::mutex g_slots_mu;
-std::map<int, SlotStreams> g_slots;
+std::mutex g_dev_mu;
+std::map<int, DeviceState> g_dev;
 
-gsf_status slot_streams(SlotStreams **out)
+gsf_status current_device(int *dev)
 {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(GSF_ERR_DEVICE, "hipGetDevice failed");
-    auto it = g_slots.find(dev);
-    if (it == g_slots.end()) {
-        SlotStreams ss{};
-        bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
-        for (int i = 0; i < kSlots && good; ++i)
-            good = hipStreamCreateWithFlags(&ss.stream[i], hipStreamNonBlocking) == hipSuccess &&
-                   hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
-        if (!good) return fail(GSF_ERR_DEVICE, "creating the batch streams failed");
-        it = g_slots.emplace(dev, ss).first;
-    }
-    *out = &it->second;
+    if (hipGetDevice(dev) != hipSuccess) return fail(GSF_ERR_DEVICE, "hipGetDevice failed");
     return GSF_OK;
 }
 
-}  // namespace
-
-gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
-                                   int32_t nfilt, gsf_box b, size_t *bytes)
+// Is `s` being captured into a graph?  Streams and symbol addresses are set
+// up outside captures only.
+bool capturing(hipStream_t s)
 {
-    gsf_status st;
-    gsf_dims largest{};
-    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
-    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
-    *bytes = find_ws(largest, ncubes);
-    return ok();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
 }
 
-gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
-                    gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
-                    float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
-                    void *stream)
+gsf_status init_streams(DeviceState &ds)
+{
+    if (ds.streams_ready) return GSF_OK;
+    bool good = hipEventCreateWithFlags(&ds.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kSlots && good; ++i)
+        good = hipStreamCreateWithFlags(&ds.stream[i], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&ds.join[i], hipEventDisableTiming) == hipSuccess;
+    if (!good) return fail(GSF_ERR_DEVICE, "creating the batch streams failed");
+    ds.streams_ready = true;
+    return GSF_OK;
+}
+
+// Check every output pointer of a batch against the inputs, the workspace
+// and each other; nothing is enqueued.
+gsf_status check_outputs(const gsf_cube *cubes, int32_t ncubes, int32_t nfilt,
+                         uint64_t *const *masks, void *const *F_out, float *const *mean_out,
+                         float *const *std_out, const void *ws, size_t need)
 {
     gsf_status st;
-    gsf_dims largest{};
-    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
-    if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
     if (!masks) return fail(GSF_ERR_INVALID_ARG, "masks is NULL");
-    const size_t need = find_ws(largest, ncubes);
-    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
-    if ((st = check_ptr(ws, 16, "ws"))) return st;
-    // Validate every output pointer before enqueueing anything.
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_cube &q = cubes[c];
         if ((st = check_ptr(q.data, 16, "cube data"))) return st;
@@ -512,8 +599,19 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
             }
         }
     }
+    return GSF_OK;
+}
+
+// Enqueue the whole path for a validated batch.  Slot i of `nslots` uses
+// bytes [i * slot_ws(L), (i+1) * slot_ws(L)) of ws; with more than one slot
+// the cubes run on the device's library streams (ss), forked from and joined
+// back to `caller`.
+gsf_status find_enqueue(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                        gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
+                        float *const *mean_out, float *const *std_out, void *ws, const Layout &L,
+                        int nslots, DeviceState *ss, hipStream_t caller)
+{
     // Largest cubes first, each to the slot with the least work so far.
-    const int nslots = find_slots(ncubes, largest);
     std::vector<int32_t> order((size_t)ncubes);
     for (int32_t c = 0; c < ncubes; ++c) order[(size_t)c] = c;
     auto vox = [&](int32_t c) { return cubes[c].dims.nx * cubes[c].dims.ny * cubes[c].dims.nz; };
@@ -526,59 +624,99 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
         slot_of[(size_t)c] = sl;
         load[(size_t)sl] += vox(c);
     }
-    const hipStream_t caller = (hipStream_t)stream;
-    std::unique_lock<std::mutex> lock(g_slots_mu, std::defer_lock);
-    SlotStreams *ss = nullptr;
+    // Spectral-pass groups: filters with equal (sigma_z, truncate), in order
+    // of first appearance, each group's members sorted by spatial radius and
+    // cut into sweeps of at most kMaxMerge filters.
+    std::vector<std::vector<int32_t>> sweeps;
+    {
+        std::vector<char> seen((size_t)nfilt, 0);
+        for (int32_t g = 0; g < nfilt; ++g) {
+            if (seen[g]) continue;
+            std::vector<int32_t> m;
+            for (int32_t j = g; j < nfilt; ++j)
+                if (!seen[j] && same_group(f[g], f[j])) m.push_back(j), seen[j] = 1;
+            std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b2) {
+                return make_taps(f[a].sigma_xy, f[a].truncate).r <
+                       make_taps(f[b2].sigma_xy, f[b2].truncate).r;
+            });
+            for (size_t i = 0; i < m.size(); i += kMaxMerge)
+                sweeps.emplace_back(m.begin() + i,
+                                    m.begin() + std::min(m.size(), i + (size_t)kMaxMerge));
+        }
+    }
     if (nslots > 1) {
-        lock.lock();
-        if ((st = slot_streams(&ss))) return st;
         if (hipEventRecord(ss->fork, caller) != hipSuccess)
             return fail(GSF_ERR_DEVICE, "gsf_find: fork event failed");
         for (int i = 0; i < nslots; ++i)
             if (hipStreamWaitEvent(ss->stream[i], ss->fork, 0) != hipSuccess)
                 return fail(GSF_ERR_DEVICE, "gsf_find: fork wait failed");
     }
-    const size_t sws = slot_ws(largest);
-    // The spectral pass depends only on (sigma_z, truncate): run it once per
-    // distinct pair and apply every filter that shares it.
-    std::vector<char> done((size_t)nfilt, 0);
+    const size_t sws = slot_ws(L);
+    const size_t cb = cube_bytes(L.largest);
     const gsf_status run = [&]() -> gsf_status {
     for (int32_t c : order) {
         const int sl = slot_of[(size_t)c];
         const hipStream_t s = nslots > 1 ? ss->stream[sl] : caller;
         char *base = (char *)ws + (size_t)sl * sws;
-        void *T1 = base;                              // in the cube's storage type
-        void *Fbuf = base + cube_bytes(largest);
-        const StatsWs w = carve_stats(base + 2 * cube_bytes(largest), largest);
+        void *T1 = base;                              // FP32
+        char *Fbuf = base + cb;                       // nF cubes
+        const StatsWs w = carve_stats(base + (size_t)(1 + L.nF) * cb, L.largest, L.nS, L.nF);
         const gsf_cube &q = cubes[c];
-        const gsf::Dims dd = to_dims(core_dims(q));   // the core: F, statistics, masks
+        const gsf_dims core = core_dims(q);
+        const gsf::Dims dd = to_dims(core);           // the core: F, statistics, masks
         const gsf::Halo h{q.dims.nx, q.dims.ny, q.dims.nz, q.halo[0], q.halo[1], q.halo[2]};
         const gsf::Store sto = to_store(q.dtype);
-        std::fill(done.begin(), done.end(), 0);
-        for (int32_t g = 0; g < nfilt; ++g) {
-            if (done[g]) continue;
-            const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
-            hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, h, tz, s);
-            if (e != hipSuccess) return device_status(e, "gsf_find launch");
-            for (int32_t j = g; j < nfilt; ++j) {
-                if (done[j] || f[j].sigma_z != f[g].sigma_z || f[j].truncate != f[g].truncate)
-                    continue;
-                done[j] = 1;
-                const int64_t o = (int64_t)c * nfilt + j;
-                void *F = (F_out && F_out[o]) ? F_out[o] : Fbuf;
-                const gsf::Taps txy = make_taps(f[j].sigma_xy, f[j].truncate);
-                int nparts = 0;
-                e = gsf::launch_yx(T1, F, w.w1, sto, dd, h, txy, w.partials, &nparts, s);
-                if (e == hipSuccess)
-                    e = nparts > 0 ? gsf::launch_mean_partials(w.partials, nparts, dd.voxels(),
-                                                               w.shift, s)
-                                   : gsf::launch_mean(F, sto, dd, w.partials, w.shift, s);
-                if (e == hipSuccess)
-                    e = gsf::launch_stats(F, sto, dd, to_box(b), w.shift, w.w1, w.w2, w.w3, w.w4,
-                                          mean_out ? mean_out[o] : nullptr,
-                                          std_out ? std_out[o] : nullptr, masks[o], k, s);
+        const gsf::Tune tune = tune_for(core, q.dtype);
+        gsf::set_active_tune(tune);
+        int32_t last_z = -1;
+        for (const std::vector<int32_t> &sw : sweeps) {
+            const int32_t g = sw[0];
+            // the spectral pass, once per group (consecutive sweeps of one
+            // group share it)
+            if (last_z < 0 || !same_group(f[last_z], f[g])) {
+                const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
+                const hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, h, tz, s);
                 if (e != hipSuccess) return device_status(e, "gsf_find launch");
+                last_z = g;
             }
+            const int n = (int)sw.size();
+            gsf::Taps txy[kMaxMerge];
+            void *F[kMaxMerge];
+            int r[kMaxMerge];
+            for (int i = 0; i < n; ++i) {
+                const int64_t o = (int64_t)c * nfilt + sw[i];
+                txy[i] = make_taps(f[sw[i]].sigma_xy, f[sw[i]].truncate);
+                r[i] = txy[i].r;
+                F[i] = (F_out && F_out[o]) ? F_out[o] : (void *)(Fbuf + (size_t)i * cb);
+            }
+            const int form = (tune.merge && n >= 2) ? gsf::merged_form(r, n) : -1;
+            int nparts[kMaxMerge] = {0, 0, 0};
+            hipError_t e = hipSuccess;
+            if (form >= 0) {
+                int np = 0;
+                e = gsf::launch_yx_merged(form, tune.merged_shape, T1, F, sto, dd, h, txy,
+                                          w.partials, &np, s);
+                for (int i = 0; i < n; ++i) nparts[i] = np;
+            }
+            if (form < 0 || e == hipErrorInvalidValue) {
+                e = hipSuccess;
+                for (int i = 0; i < n && e == hipSuccess; ++i)
+                    e = gsf::launch_yx(T1, F[i], w.w1, sto, dd, h, txy[i],
+                                       w.partials + (size_t)i * gsf::kMaxPartials, &nparts[i], s);
+            }
+            for (int i = 0; i < n && e == hipSuccess; ++i) {
+                const int64_t o = (int64_t)c * nfilt + sw[i];
+                double *parts = w.partials + (size_t)i * gsf::kMaxPartials;
+                double *shift = w.shift + i;
+                e = nparts[i] > 0
+                        ? gsf::launch_mean_partials(parts, nparts[i], dd.voxels(), shift, s)
+                        : gsf::launch_mean(F[i], sto, dd, parts, shift, s);
+                if (e == hipSuccess)
+                    e = gsf::launch_stats(F[i], sto, dd, to_box(b), shift, w.w1, w.w2, w.w3,
+                                          w.w4, mean_out ? mean_out[o] : nullptr,
+                                          std_out ? std_out[o] : nullptr, masks[o], k, s);
+            }
+            if (e != hipSuccess) return device_status(e, "gsf_find launch");
         }
     }
     return GSF_OK;
@@ -591,6 +729,121 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                 return fail(GSF_ERR_DEVICE, "gsf_find: join failed");
     }
     return run != GSF_OK ? run : ok();
+}
+
+// Serialises the enqueueing of calls that use the per-device state (the
+// batch streams).
+std::mutex g_enqueue_mu;
+
+}  // namespace
+
+gsf_status gsf_init(void)
+{
+    int dev = 0;
+    gsf_status st;
+    if ((st = current_device(&dev))) return st;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceState &ds = g_dev[dev];
+    if ((st = init_streams(ds))) return st;
+    return ok();
+}
+
+int32_t gsf_size_class(gsf_dims core)
+{
+    if (check_dims(core) != GSF_OK) return -1;
+    return size_class(core);
+}
+
+gsf_status gsf_tuning_set(int32_t cls, gsf_dtype t, const gsf_tuning *cfg)
+{
+    gsf_status st;
+    if ((st = check_dtype(t, "dtype")) || (st = check_tuning(cfg))) return st;
+    if (cls < -1 || cls >= kSizeClasses)
+        return fail(GSF_ERR_INVALID_ARG, "size class must be -1 or in [0, %d)", kSizeClasses);
+    gsf::Tune v;
+    v.merge = cfg->merge_sweeps;
+    v.merged_shape = cfg->merged_shape;
+    v.sweep_blocks = cfg->sweep_blocks;
+    v.yz_waves = cfg->yz_waves;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int c = 0; c < kSizeClasses; ++c)
+        if (cls < 0 || c == cls) g_tune[(int)t][c] = v;
+    return ok();
+}
+
+gsf_status gsf_tuning_get(int32_t cls, gsf_dtype t, gsf_tuning *cfg)
+{
+    gsf_status st;
+    if ((st = check_dtype(t, "dtype"))) return st;
+    if (!cfg) return fail(GSF_ERR_INVALID_ARG, "tuning pointer is NULL");
+    if (cls < 0 || cls >= kSizeClasses)
+        return fail(GSF_ERR_INVALID_ARG, "size class must be in [0, %d)", kSizeClasses);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const gsf::Tune &v = g_tune[(int)t][cls];
+    cfg->merge_sweeps = v.merge;
+    cfg->merged_shape = v.merged_shape;
+    cfg->sweep_blocks = v.sweep_blocks;
+    cfg->yz_waves = v.yz_waves;
+    return ok();
+}
+
+gsf_status gsf_tuning_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &row : g_tune)
+        for (auto &v : row) v = gsf::Tune{};
+    return ok();
+}
+
+gsf_status gsf_find_workspace_size(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
+                                   int32_t nfilt, gsf_box b, size_t *bytes)
+{
+    gsf_status st;
+    gsf_dims largest{};
+    if (!bytes) return fail(GSF_ERR_INVALID_ARG, "bytes is NULL");
+    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
+    *bytes = find_ws(find_layout(cubes, ncubes, f, nfilt, b, largest), ncubes);
+    return ok();
+}
+
+gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
+                    gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
+                    float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
+                    void *stream)
+{
+    gsf_status st;
+    gsf_dims largest{};
+    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
+    if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
+    if (!masks) return fail(GSF_ERR_INVALID_ARG, "masks is NULL");
+    const Layout L = find_layout(cubes, ncubes, f, nfilt, b, largest);
+    const size_t need = find_ws(L, ncubes);
+    if (ws_bytes < need) return fail(GSF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((st = check_ptr(ws, 16, "ws"))) return st;
+    if ((st = check_outputs(cubes, ncubes, nfilt, masks, F_out, mean_out, std_out, ws, need)))
+        return st;
+    const int nslots = find_slots(ncubes, L);
+    const hipStream_t caller = (hipStream_t)stream;
+    DeviceState *ss = nullptr;
+    std::unique_lock<std::mutex> lock(g_enqueue_mu, std::defer_lock);
+    if (nslots > 1) {
+        lock.lock();
+        int dev = 0;
+        if ((st = current_device(&dev))) return st;
+        {
+            std::lock_guard<std::mutex> lk(g_dev_mu);
+            ss = &g_dev[dev];
+            if (!ss->streams_ready) {
+                if (capturing(caller))
+                    return fail(GSF_ERR_UNSUPPORTED,
+                                "gsf_find: a batch captured into a graph needs the library "
+                                "streams; call gsf_init() before the capture");
+                if ((st = init_streams(*ss))) return st;
+            }
+        }
+    }
+    return find_enqueue(cubes, ncubes, f, nfilt, b, k, masks, F_out, mean_out, std_out, ws,
+                        L, nslots, ss, caller);
 }
 
 }  // extern "C"

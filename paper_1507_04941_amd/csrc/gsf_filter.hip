@@ -27,6 +27,7 @@
 
 #include "gsf_device.h"
 #include "gsf_internal.h"
+#include "gsf_merged.h"
 
 namespace gsf {
 namespace {
@@ -76,7 +77,7 @@ constexpr int kZRows = 16;
 
 template <int R, typename St, bool A, bool MUL = false>
 __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
-                                                         St *__restrict__ out, int64_t nrows,
+                                                         float *__restrict__ out, int64_t nrows,
                                                          int64_t nz, int64_t NZ, int64_t zoff,
                                                          Taps t, const St *__restrict__ wv = nullptr)
 {
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
     // below 2^31 bytes)
     const uint32_t om = (uint32_t)((zm + zoff) * SZ);
     const uint32_t oh = halo ? (uint32_t)((zh + zoff) * SZ) : kOOB;
-    const uint32_t os = (uint32_t)(zm * SZ);
+    const uint32_t os = (uint32_t)(zm * sizeof(float));
     auto fetch_one = [&](const St *src, int64_t r, float4 &m, float &h) {
         if constexpr (A) {
             const St *row = src + r * NZ + zoff;
@@ -160,9 +161,9 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
         if constexpr (A) {
             if (mine) store4(out + r * nz + zm, acc);
         } else {
-            const __amdgpu_buffer_rsrc_t ro = buf(out + r * nz, (uint32_t)(nz * SZ));
+            const __amdgpu_buffer_rsrc_t ro = buf(out + r * nz, (uint32_t)(nz * sizeof(float)));
 #pragma unroll
-            for (int k = 0; k < 4; ++k) sbuf_st<St>(ro, acc[k], os + (uint32_t)k * SZ);
+            for (int k = 0; k < 4; ++k) buf_st(ro, acc[k], os + (uint32_t)k * sizeof(float));
         }
     }
 }
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
 // result D is not stored: each output becomes N / D (0 where D = 0), read
 // and written in place by the same lane.
 template <int R, int P, int NW, typename St, bool DIV = false>
-__global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
+__global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
                                                   St *F, int64_t nx, int64_t ny,
                                                   int64_t nz, int64_t xchunk, Taps t,
                                                   double *__restrict__ partials, int64_t NX,
@@ -203,8 +204,9 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     // T1 is NX x NY rows of nz (core z); F is the nx x ny x nz core, whose
     // (x, y) reads T1 at (x + hx, y + hy)
     constexpr int64_t SZ = sizeof(St);
+    constexpr int64_t TSZ = sizeof(float);                        // T1 is FP32
     const int64_t tplane = NY * nz;
-    const uint32_t tplane_b = (uint32_t)(tplane * SZ);
+    const uint32_t tplane_b = (uint32_t)(tplane * TSZ);
     const int64_t plane = ny * nz;
     const uint32_t plane_b = (uint32_t)(plane * SZ);
     const uint32_t row_b = (uint32_t)(nz * SZ);
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
         const int tr = wave + i * NW;
-        ldo[i] = tr < TR ? (uint32_t)(((yb + hy - R + tr) * nz + z) * SZ) : kOOB;
+        ldo[i] = tr < TR ? (uint32_t)(((yb + hy - R + tr) * nz + z) * TSZ) : kOOB;
     }
     const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * SZ) : kOOB;
 
@@ -229,19 +231,18 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     const int64_t p_end = xb - 1 + R;                       // inclusive
 
     // a plane outside [0, nx) gets an empty range, so its rows read 0
-    // loads stay raw until stored to LDS two planes later
-    auto load_plane = [&](int64_t xq, raw_t<St> (&r)[LW]) {
+    auto load_plane = [&](int64_t xq, float (&r)[LW]) {
         const int64_t xt = xq + hx;                          // T1 plane of core plane xq
         const bool in = xt >= 0 && xt < NX;
         const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xt : 0) * tplane, in ? tplane_b : 0u);
 #pragma unroll
-        for (int i = 0; i < LW; ++i) r[i] = sbuf_ld_raw<St>(rt, ldo[i]);
+        for (int i = 0; i < LW; ++i) r[i] = buf_ld(rt, ldo[i]);
     };
-    auto store_stage = [&](int st, const raw_t<St> (&r)[LW]) {
+    auto store_stage = [&](int st, const float (&r)[LW]) {
 #pragma unroll
         for (int i = 0; i < LW; ++i) {
             const int tr = wave + i * NW;
-            if (tr < TR) stage[st][tr][lane] = from_raw<St>(r[i]);
+            if (tr < TR) stage[st][tr][lane] = r[i];
         }
     };
     // prologue: plane p_start in LDS, planes p_start+1 .. p_start+D in
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const St *__restrict__ T,
     // mod L) and the last turn runs to its end: the surplus planes read 0 or
     // feed only outputs past xb, which are never written.  (Branching around
     // them defeats the load pipelining.)
-    raw_t<St> rq[D][LW];
+    float rq[D][LW];
     load_plane(p_start, rq[0]);
     store_stage((int)(p_start & (S - 1)), rq[0]);
 #pragma unroll
@@ -343,7 +344,7 @@ hipError_t zpass_impl(const void *in_, void *out_, Dims d, const Halo &h, const 
 {
     const St *in = (const St *)in_;
     const St *w = (const St *)w_;
-    St *out = (St *)out_;
+    float *out = (float *)out_;
     const int64_t rows = h.NX * h.NY;
     const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     prof::Scope scope(MUL ? "k_zpass_r_mul" : kernel_name<St>("k_zpass_r", R), s);
@@ -372,7 +373,8 @@ hipError_t yx_r(const void *T, void *F, Dims d, const Halo &h, const Taps &txy, 
     const int64_t ty = (d.ny + NW * P - 1) / (NW * P);
     // Split x so the grid has enough blocks to fill the chip; each chunk
     // re-reads 2R planes of halo.
-    int64_t nxc = (512 + tz * ty - 1) / (tz * ty);
+    const int64_t target = active_tune().sweep_blocks;
+    int64_t nxc = (target + tz * ty - 1) / (tz * ty);
     const int64_t max_chunks = d.nx / (4 * (2 * R + 1)) > 0 ? d.nx / (4 * (2 * R + 1)) : 1;
     if (nxc > max_chunks) nxc = max_chunks;
     if (nxc < 1) nxc = 1;
@@ -385,7 +387,7 @@ hipError_t yx_r(const void *T, void *F, Dims d, const Halo &h, const Taps &txy, 
     if (DIV) partials = nullptr;
     if (nparts && DIV) *nparts = 0;
     prof::Scope scope(DIV ? "k_yx_r_div" : kernel_name<St>("k_yx_r", R), s);
-    hipLaunchKernelGGL((k_yx_r<R, P, NW, St, DIV>), grid, dim3(64 * NW), 0, s, (const St *)T, (St *)F,
+    hipLaunchKernelGGL((k_yx_r<R, P, NW, St, DIV>), grid, dim3(64 * NW), 0, s, (const float *)T, (St *)F,
                        d.nx, d.ny, d.nz, xchunk, txy, partials, h.NX, h.NY, (int64_t)h.hx,
                        (int64_t)h.hy);
     return hipGetLastError();
@@ -440,6 +442,7 @@ const YXFn *yxdivtab_of(std::integer_sequence<int, R...>)
     return tab;
 }
 
+
 }  // namespace
 
 bool zpass_fast(int rz) { return rz >= 1 && rz <= kMaxFastRz; }
@@ -471,6 +474,39 @@ hipError_t launch_yx_div_fast(const float *T1, float *F, Dims d, const Taps &txy
     if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
     return yxdivtab_of(std::make_integer_sequence<int, kMaxFastRxy>{})[txy.r](
         T1, F, d, no_halo(d), txy, nullptr, nullptr, s);
+}
+
+int merged_form(const int *r, int nf)
+{
+    if (nf < 2 || nf > 3) return -1;
+    for (int i = 0; i < kMergedForms; ++i) {
+        const MergedRadii &m = kMergedRadii[i];
+        if (m.nf != nf) continue;
+        bool same = true;
+        for (int f = 0; f < nf; ++f) same = same && m.r[f] == r[f];
+        if (same) return i;
+    }
+    return -1;
+}
+
+hipError_t launch_yx_merged(int form, int shape, const void *T1, void *const *F, Store st,
+                            Dims d, const Halo &h, const Taps *txy, double *partials,
+                            int *nparts, hipStream_t s)
+{
+    if (form < 0 || form >= kMergedForms || shape < 0 || shape >= kMergedShapes)
+        return hipErrorInvalidValue;
+    const MergedRadii &m = kMergedRadii[form];
+    for (int f = 0; f < m.nf; ++f)
+        if (txy[f].r != m.r[f] || !F[f]) return hipErrorInvalidValue;
+    if (!yx_fast(m.r[m.nf - 1], d) || !yx_fast(m.r[m.nf - 1], Dims{h.NX, h.NY, d.nz}))
+        return hipErrorInvalidValue;
+    MergedFn fn = nullptr;
+    switch (st) {
+    case Store::F16: fn = merged_fn_f16(form, shape); break;
+    case Store::BF16: fn = merged_fn_bf16(form, shape); break;
+    default: fn = merged_fn_f32(form, shape); break;
+    }
+    return fn(T1, F, d, h, txy, partials, nparts, s);
 }
 
 hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,

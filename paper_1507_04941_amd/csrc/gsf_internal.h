@@ -50,6 +50,29 @@ struct Box {
     int bx, by, bz;
 };
 
+// Launch configuration of the kernels with more than one compiled shape
+// (what the tuning entries of include/gsf.h set; defaults are the measured
+// best on the 512x512x1024 cube):
+//   merge         1: one merged spatial sweep per sigma_z group where a form is
+//                 compiled; 0: one sweep per filter
+//   merged_shape  block shape of the merged sweep (kMergedShape index)
+//   sweep_blocks  blocks a spatial sweep aims for before it splits x into
+//                 chunks (each chunk re-reads 2r planes)
+//   yz_waves      waves per block of the yz window kernel (3, 5 or 9; 0: the
+//                 one that walks the fewest columns for the cube's depth)
+struct Tune {
+    int merge = 1;
+    int merged_shape = 0;
+    int sweep_blocks = 512;
+    int yz_waves = 0;
+};
+
+// The configuration of the call being enqueued on this thread: the API layer
+// sets it per cube before launching; launchers read it (enqueueing is
+// synchronous, so a thread-local value cannot be seen by another call).
+const Tune &active_tune();
+void set_active_tune(const Tune &t);
+
 // Number of per-block partial sums used for the global shift.
 constexpr int kShiftBlocks = 1024;
 
@@ -81,6 +104,19 @@ hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const H
                              const Taps &tz, hipStream_t s);
 hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,
                           const Taps &txy, double *partials, int *nparts, hipStream_t s);
+// Merged spatial sweeps: one kernel applies the spatial passes of 2 or 3
+// filters that share T1 (equal sigma_z).  merged_form(r, nf) returns the
+// index of the compiled form for radii r[0] < r[1] (< r[2]), or -1.
+// launch_yx_merged writes F[i] for taps txy[i] (radius r[i]) with block
+// shape `shape` (0: 2 rows per lane, 8 waves; 1: 1 row, 8 waves; 2: 2 rows,
+// 4 waves); its shift partials go to partials + i * kMaxPartials (*nparts
+// blocks each, 0 if not written).  hipErrorInvalidValue when the form does
+// not fit the call.
+constexpr int kMaxMergedR = 12;
+int merged_form(const int *r, int nf);
+hipError_t launch_yx_merged(int form, int shape, const void *T1, void *const *F, Store st,
+                            Dims d, const Halo &h, const Taps *txy, double *partials,
+                            int *nparts, hipStream_t s);
 // FP32 weighted convolution (Eq. 1) pieces, no halo; hipErrorInvalidValue
 // when the radius has no compiled form.  T1 = gz * (in * w) along z; and
 // F = F / (gxy * (gxy * T1 along y) along x), 0 where the divisor is 0, in
@@ -98,7 +134,8 @@ hipError_t launch_stats_fast(const void *F, Store st, Dims d, Box b, const doubl
                              hipStream_t s);
 
 // Kernel launchers.  All enqueue on `s` and return hipGetLastError().
-// Cubes passed as void * hold elements of storage type st.
+// Cubes passed as void * hold elements of storage type st, except the
+// spectral intermediate T1 (and the generic path's tmp), which are FP32.
 // Spectral pass: T1 = gz * in along z.  d: the core; h: the input array.
 hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Halo &h,
                         const Taps &tz, hipStream_t s);

@@ -24,7 +24,7 @@ constexpr int kBlock = 256;   // four wave64s along z
 // with coalesced loads, then every lane reads its 2r+1 neighbours from LDS.
 template <typename St>
 __global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
-                                                  St *__restrict__ out, int64_t nz, int64_t NZ,
+                                                  float *__restrict__ out, int64_t nz, int64_t NZ,
                                                   int64_t zoff, Taps t)
 {
     extern __shared__ float tile[];
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
     if (z < nz) {
         float acc = 0.0f;
         for (int o = 0; o <= 2 * r; ++o) acc = fmaf(t.g[o], tile[threadIdx.x + o], acc);
-        out[row * nz + z] = narrow<St>(acc);
+        out[row * nz + z] = acc;
     }
 }
 
@@ -50,9 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_zpass(const St *__restrict__ in,
 // input rows of NYi rows per plane: along y, input row y + off + o of plane X
 // (inside [0, NYi)); along x, row y of plane X + off + o (inside [0, NXi)).
 // Lanes run along z so every tap load is a coalesced row read.
-template <typename St>
-__global__ __launch_bounds__(kBlock) void k_strided_pass(const St *__restrict__ in,
-                                                         St *__restrict__ out, int64_t NXi,
+template <typename Si, typename So>
+__global__ __launch_bounds__(kBlock) void k_strided_pass(const Si *__restrict__ in,
+                                                         So *__restrict__ out, int64_t NXi,
                                                          int64_t NYi, int64_t NYo, int64_t nz,
                                                          int axis_x, int64_t off, Taps t)
 {
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_strided_pass(const St *__restrict__ 
         if (xi >= 0 && xi < NXi && yi >= 0 && yi < NYi)
             acc = fmaf(t.g[o + r], widen(in[(xi * NYi + yi) * nz + z]), acc);
     }
-    out[row * nz + z] = narrow<St>(acc);
+    out[row * nz + z] = narrow<So>(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +308,7 @@ hipError_t launch_zpass(const void *in, void *T1, Store st, Dims d, const Halo &
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
         hipLaunchKernelGGL(k_zpass<St>, grid, dim3(kBlock), (kBlock + 2 * tz.r) * sizeof(float), s,
-                           (const St *)in, (St *)T1, d.nz, h.NZ, (int64_t)h.hz, tz);
+                           (const St *)in, (float *)T1, d.nz, h.NZ, (int64_t)h.hz, tz);
         return hipGetLastError();
     });
 }
@@ -322,18 +322,20 @@ hipError_t launch_yx(const void *T1, void *F, void *tmp, Store st, Dims d, const
     return with_store(st, [&](auto *tag) {
         using St = GSF_STORE_T(tag);
         {
-            // y pass: T1 (NX x NY rows) -> tmp (NX x ny rows)
+            // y pass: T1 (NX x NY rows, FP32) -> tmp (NX x ny rows, FP32)
             prof::Scope scope_("k_strided_pass", s);
-            hipLaunchKernelGGL(k_strided_pass<St>, dim3((unsigned)(h.NX * d.ny), ztiles(d.nz)),
-                               dim3(kBlock), 0, s, (const St *)T1, (St *)tmp, h.NX, h.NY, d.ny,
-                               d.nz, 0, (int64_t)h.hy, txy);
+            hipLaunchKernelGGL((k_strided_pass<float, float>),
+                               dim3((unsigned)(h.NX * d.ny), ztiles(d.nz)), dim3(kBlock), 0, s,
+                               (const float *)T1, (float *)tmp, h.NX, h.NY, d.ny, d.nz, 0,
+                               (int64_t)h.hy, txy);
         }
         {
-            // x pass: tmp (NX x ny rows) -> F (nx x ny rows)
+            // x pass: tmp (NX x ny rows) -> F (nx x ny rows, storage type)
             prof::Scope scope_("k_strided_pass", s);
-            hipLaunchKernelGGL(k_strided_pass<St>, dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)),
-                               dim3(kBlock), 0, s, (const St *)tmp, (St *)F, h.NX, d.ny, d.ny,
-                               d.nz, 1, (int64_t)h.hx, txy);
+            hipLaunchKernelGGL((k_strided_pass<float, St>),
+                               dim3((unsigned)(d.nx * d.ny), ztiles(d.nz)), dim3(kBlock), 0, s,
+                               (const float *)tmp, (St *)F, h.NX, d.ny, d.ny, d.nz, 1,
+                               (int64_t)h.hx, txy);
         }
         return hipGetLastError();
     });

@@ -683,6 +683,8 @@ hipError_t box_yz(const void *F_, Dims d, int bz, const double *shift, float *G,
             const int64_t c = (d.nz + 64 * (nw - 1) - 1) / (64 * (nw - 1)) * nw;
             if (nw == 9 || c < cost) best = nw, cost = c;
         }
+        const int tuned = active_tune().yz_waves;
+        if (tuned == 3 || tuned == 5 || tuned == 9) best = tuned;
         if (best == 3) return yz_seg<BY, 3, St>(F, d, bz, shift, G, s);
         if (best == 5) return yz_seg<BY, 5, St>(F, d, bz, shift, G, s);
         return yz_seg<BY, 9, St>(F, d, bz, shift, G, s);

@@ -63,7 +63,12 @@ def test_workspace_sizes(L):
     n2 = ctypes.c_size_t(0)
     assert L.gsf_local_stats_workspace_size(B.Dims(64, 64, 128), B.Box(32, 32, 32),
                                             ctypes.byref(n2)) == 0
-    assert n2.value >= 4 * 64 * 64 * 128 * 4
+    # the fast statistics path: two FP32 cubes of window-sum pairs + shift partials
+    assert 2 * 64 * 64 * 128 * 4 <= n2.value < 3 * 64 * 64 * 128 * 4
+    n4 = ctypes.c_size_t(0)
+    assert L.gsf_local_stats_workspace_size(B.Dims(64, 64, 128), B.Box(12, 32, 32),
+                                            ctypes.byref(n4)) == 0
+    assert n4.value - n2.value == 2 * 64 * 64 * 128 * 4     # generic path: four cubes
     cubes = (B.Cube * 2)()
     cubes[0].data = 256
     cubes[0].dims = B.Dims(64, 64, 128)
@@ -165,3 +170,56 @@ def test_find_validation(L):
     cubes[0].dtype = 0
     masks2 = (ctypes.c_void_p * 1)(4096 + 64)  # mask overlaps the cube
     assert L.gsf_find(cubes, 1, filt, 1, box, 4.0, masks2, None, None, None, ws, need, None) == 1
+
+
+def test_tuning_table_validation(L):
+    t = B.Tuning(1, 0, 512, 0)
+    assert L.gsf_tuning_set(-1, 0, ctypes.byref(t)) == 0
+    for bad in (B.Tuning(2, 0, 512, 0), B.Tuning(1, 3, 512, 0), B.Tuning(1, -1, 512, 0),
+                B.Tuning(1, 0, 63, 0), B.Tuning(1, 0, 70000, 0), B.Tuning(1, 0, 512, 4)):
+        assert L.gsf_tuning_set(-1, 0, ctypes.byref(bad)) == B.GSF_ERR_INVALID_ARG
+    assert L.gsf_tuning_set(41, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
+    assert L.gsf_tuning_set(-2, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
+    assert L.gsf_tuning_set(3, 7, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
+    assert L.gsf_tuning_set(3, 0, None) == B.GSF_ERR_INVALID_ARG
+    t2 = B.Tuning(0, 2, 4096, 5)
+    assert L.gsf_tuning_set(20, 1, ctypes.byref(t2)) == 0
+    got = B.Tuning()
+    assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
+    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves) == (0, 2, 4096, 5)
+    assert L.gsf_tuning_get(20, 0, ctypes.byref(got)) == 0
+    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves) == (1, 0, 512, 0)
+    assert L.gsf_tuning_get(-1, 0, ctypes.byref(got)) == B.GSF_ERR_INVALID_ARG
+    assert L.gsf_tuning_reset() == 0
+    assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
+    assert (got.merge_sweeps, got.sweep_blocks) == (1, 512)
+
+
+def test_size_class(L):
+    assert L.gsf_size_class(B.Dims(1, 1, 1)) == 0
+    assert L.gsf_size_class(B.Dims(512, 512, 1024)) == 28
+    assert L.gsf_size_class(B.Dims(3, 3, 3)) == 4          # 27 voxels
+    assert L.gsf_size_class(B.Dims(0, 3, 3)) == -1
+
+
+def test_find_workspace_counts_merged_filters(L):
+    # one spectral pass shared by three filters needs three F buffers; one
+    # filter per pass needs one
+    cubes = (B.Cube * 1)()
+    cubes[0].data = 256
+    cubes[0].dims = B.Dims(64, 64, 128)
+    cb = 64 * 64 * 128 * 4
+
+    def ws(filters, box=B.Box(16, 16, 16)):
+        filt = (B.Filter * len(filters))(*[B.Filter(a, b, 3) for a, b in filters])
+        n = ctypes.c_size_t(0)
+        assert L.gsf_find_workspace_size(cubes, 1, filt, len(filters), box, ctypes.byref(n)) == 0
+        return n.value
+
+    one = ws([(1, 1), (2, 2), (2, 4)])
+    three = ws([(1, 2), (2, 2), (4, 2)])
+    assert three - one == 2 * cb + 2 * (((1 << 16) * 8 + 255) // 256 * 256)
+    # T1 + F + two window-sum cubes (+ shift partials) for the fast statistics
+    assert one >= 4 * cb and one < 4 * cb + (1 << 20)
+    # four cubes of window sums on the generic statistics path (box 128 > 64)
+    assert ws([(1, 1)], B.Box(128, 16, 16)) - ws([(1, 1)]) == 2 * cb

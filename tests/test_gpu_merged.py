@@ -1,0 +1,104 @@
+"""Merged spatial sweeps and launch tunings on the GPU.  The filters of a
+group that shares one spectral pass go through one merged sweep where a form
+is compiled; its F is bit for bit the single-filter sweep's (gsf_filter3d),
+for every block shape and x split, with halos and 16-bit storage.  Every
+tuning gives results that match the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1507_04941_amd import binding as B
+from paper_1507_04941_amd import synth
+from tests.parity import (REL16, REL16_F, check_filtered, check_mask, check_stats, cube_scale,
+                          log, round16, sigma_f)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+BOX = (16, 8, 32)
+# banks: the measured bank (two merged triples, radii 3, 6, 12), the three
+# pair forms, and a group of four (a merged triple plus a single sweep)
+BANKS = {
+    "six": [(1.0, 2.0), (1.0, 8.0), (2.0, 2.0), (2.0, 8.0), (4.0, 2.0), (4.0, 8.0)],
+    "pairs": [(2.0, 3.0), (1.0, 3.0), (4.0, 1.5), (1.0, 1.5), (4.0, 5.0), (2.0, 5.0)],
+    "four": [(4.0, 2.0), (1.0, 2.0), (1.5, 2.0), (2.0, 2.0)],
+}
+TUNINGS = [dict(merged_shape=0), dict(merged_shape=1), dict(merged_shape=2),
+           dict(merged_shape=0, sweep_blocks=64), dict(merged_shape=1, sweep_blocks=4096),
+           dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5)]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    B.tuning_reset()
+    yield
+    B.tuning_reset()
+
+
+def _gpu(a, dt=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dt).to(DEV)
+
+
+@pytest.mark.parametrize("bank", sorted(BANKS))
+@pytest.mark.parametrize("name", ["f32", "f16"])
+def test_merged_F_equals_single_filter_sweeps(bank, name):
+    filters = BANKS[bank]
+    shape, halo = (44, 37, 150), (5, 4, 9)
+    d = synth.make_cube(shape, n_sources=5, seed=81)
+    dt = torch.float32 if name == "f32" else torch.float16
+    if name != "f32":
+        d = round16(d, name)
+    g = _gpu(d, dt)
+    core = tuple(s - 2 * h for s, h in zip(shape, halo))
+    # single-filter reference: gsf_filter3d on the whole array, cut to the core
+    single = []
+    for f in filters:
+        Fs = B.filter3d(g, f)
+        single.append(Fs[halo[0]:shape[0] - halo[0], halo[1]:shape[1] - halo[1],
+                         halo[2]:shape[2] - halo[2]].contiguous())
+    for cfg in TUNINGS:
+        B.tuning_reset()
+        B.tuning_set(cfg, -1, dt)
+        out = B.find(g, filters, BOX, 4.0, want_F=True, halos=halo)
+        torch.cuda.synchronize()
+        for j in range(len(filters)):
+            assert out["F"][0][j].shape == core
+            assert torch.equal(out["F"][0][j], single[j]), (bank, name, cfg, filters[j])
+        log(f"  {bank} {name} {cfg}: F bit-identical to the single sweeps")
+
+
+@pytest.mark.parametrize("cfg", TUNINGS)
+def test_tunings_match_oracle(cfg):
+    filters = BANKS["six"]
+    shape = (40, 48, 140)
+    d = synth.make_cube(shape, n_sources=6, seed=82)
+    B.tuning_set(cfg)
+    out = B.find(_gpu(d), filters, BOX, 4.0, want_F=True, want_stats=True)
+    ref = oracle.find(d, filters, BOX, 4.0, want_F=True, want_stats=True)
+    scale = cube_scale(d)
+    worst = []
+    for j, f in enumerate(filters):
+        wf = check_filtered(out["F"][0][j].cpu().numpy(), ref["F"][j], f, scale, what=f"F{f}")
+        wm, ws = check_stats(out["mean"][0][j].cpu().numpy(), out["std"][0][j].cpu().numpy(),
+                             ref["mean"][j], ref["std"][j], sigma_f(f) * scale, what=f"stats{f}")
+        band = check_mask(B.unpack_mask(out["mask"][0][j], shape), ref["F"][j], ref["mean"][j],
+                          ref["std"][j], 4.0, f, scale, what=f"mask{f}")
+        worst.append(max(wf, wm, ws))
+    log(f"  {cfg}: worst error/bound {max(worst):.3g}")
+
+
+def test_tuning_table_is_per_size_class_and_dtype():
+    small = (16, 16, 64)                           # 2^14 voxels
+    cls = B.size_class(small)
+    assert cls == 14
+    B.tuning_set(dict(merge_sweeps=0, sweep_blocks=128), cls, torch.float16)
+    assert B.tuning_get(cls, torch.float16)["merge_sweeps"] == 0
+    assert B.tuning_get(cls, torch.float32)["merge_sweeps"] == 1
+    assert B.tuning_get(cls + 1, torch.float16)["merge_sweeps"] == 1
+    d = synth.make_cube(small, n_sources=1, seed=83)
+    a = B.find(_gpu(d, torch.float16), BANKS["six"], BOX, 4.0, want_F=True)
+    B.tuning_reset()
+    b = B.find(_gpu(d, torch.float16), BANKS["six"], BOX, 4.0, want_F=True)
+    for j in range(6):
+        assert torch.equal(a["F"][0][j], b["F"][0][j])
