@@ -155,10 +155,11 @@ gsf_status gsf_threshold(const void *F, gsf_dtype t, const float *mean, const fl
 /* ---- Library set-up ---- */
 
 /* Create the library's per-device state on the current device, once: the
- * streams a multi-cube gsf_find forks onto.  Optional (they are otherwise
- * created by the first call that needs them), but required before a graph
- * capture whose first such call is captured: streams are not created inside a
- * capture (gsf_find then returns GSF_ERR_UNSUPPORTED).  Idempotent;
+ * streams a multi-cube gsf_find forks onto and the address of the
+ * gsf_find_noalloc scratch.  Optional (they are otherwise set up by the first
+ * call that needs them), but required before a graph capture whose first such
+ * call is captured: this state is not set up inside a capture (gsf_find and
+ * gsf_find_noalloc then return GSF_ERR_UNSUPPORTED).  Idempotent;
  * GSF_ERR_DEVICE if a HIP call fails. */
 gsf_status gsf_init(void);
 
@@ -198,6 +199,36 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
                     gsf_box b, double k, uint64_t *const *masks, void *const *F_out,
                     float *const *mean_out, float *const *std_out, void *ws, size_t ws_bytes,
                     void *stream);
+
+/* ---- gsf_find for callers that cannot allocate ---- */
+
+/* Size of the device scratch gsf_find_noalloc works in: a file-scope array of
+ * the library, one copy per device, held from the library's first use on that
+ * device until the process ends. */
+#define GSF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): gsf_find with the same
+ * arguments, results and definitions, minus the workspace.  The workspace
+ * gsf_find would need for ONE slot lives in the library's scratch array
+ * instead, and the cubes run one after another on `stream` (no library
+ * streams).  The call performs no device allocation or free.
+ * Limit: one slot of gsf_find's workspace layout (FP32 spectral
+ * intermediate, one FP32-sized F per filter sharing it, two window-sum cubes,
+ * shift partials; see gsf_find_workspace_size) must fit in
+ * GSF_NOALLOC_SCRATCH_BYTES; otherwise GSF_ERR_BUDGET and nothing is
+ * enqueued.  With filters of at most three per sigma_z group that is about
+ * 2^23 voxels for the batch's largest array.
+ * The scratch is shared by every call on a device and keeps the last call's
+ * contents (every scratch byte a call reads is written by that call first):
+ * calls that overlap on one device race, so the caller serialises them (one
+ * stream, or events).  The scratch address of the current device is looked up
+ * by gsf_init or by the first call outside a capture; a first call inside a
+ * capture returns GSF_ERR_UNSUPPORTED. */
+gsf_status gsf_find_noalloc(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
+                            int32_t nfilt, gsf_box b, double k, uint64_t *const *masks,
+                            void *const *F_out, float *const *mean_out, float *const *std_out,
+                            void *stream);
 
 /* ---- Launch tuning ---- */
 

@@ -76,6 +76,9 @@ SIGNATURES = [
     ("gsf_find", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter), ctypes.c_int32,
                        Box, ctypes.c_double, ctypes.POINTER(_P), ctypes.POINTER(_P),
                        ctypes.POINTER(_P), ctypes.POINTER(_P), _P, _SZ, _P]),
+    ("gsf_find_noalloc", _ST, [ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(Filter),
+                               ctypes.c_int32, Box, ctypes.c_double, ctypes.POINTER(_P),
+                               ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
     ("gsf_init", _ST, []),
     ("gsf_size_class", ctypes.c_int32, [Dims]),
     ("gsf_tuning_set", _ST, [ctypes.c_int32, ctypes.c_int, ctypes.POINTER(Tuning)]),
@@ -298,10 +301,12 @@ def find_workspace_size(cubes, filters, box, halos=None) -> int:
 
 class FindPlan:
     """Pre-marshalled gsf_find call over fixed cubes and output buffers, so a
-    timed loop only re-issues the C call."""
+    timed loop only re-issues the C call.  With ``noalloc`` the plan calls
+    gsf_find_noalloc, which works in the library's own scratch (no workspace
+    tensor is allocated)."""
 
     def __init__(self, cubes, filters, box, k: float, want_F: bool = False,
-                 want_stats: bool = False, halos=None):
+                 want_stats: bool = False, halos=None, noalloc: bool = False):
         self.cubes = [_cube(c, f"cubes[{i}]", storage=True) for i, c in enumerate(cubes)]
         self.filters = [tuple(f) for f in filters]
         self.halos = _halos(halos, len(self.cubes))
@@ -330,12 +335,21 @@ class FindPlan:
         self._F = ptrs(self.F)
         self._mu = ptrs(self.mean)
         self._sd = ptrs(self.std)
-        need = find_workspace_size(self.cubes, self.filters, box, self.halos)
-        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.noalloc = bool(noalloc)
+        if self.noalloc:
+            self.ws = None
+        else:
+            need = find_workspace_size(self.cubes, self.filters, box, self.halos)
+            self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
         self.device = dev
 
     def run(self, stream: int | None = None) -> None:
         s = _stream(self.device) if stream is None else stream
+        if self.noalloc:
+            _check(lib().gsf_find_noalloc(self._carr, len(self.cubes), self._farr,
+                                          len(self.filters), self._box, self.k, self._m, self._F,
+                                          self._mu, self._sd, s))
+            return
         _check(lib().gsf_find(self._carr, len(self.cubes), self._farr, len(self.filters), self._box,
                               self.k, self._m, self._F, self._mu, self._sd, self.ws.data_ptr(),
                               self.ws.numel(), s))
@@ -392,6 +406,22 @@ def profile_collect() -> dict:
         _check(L.gsf_profile_entry(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)))
         out[name.value.decode()] = (int(cnt.value), float(ms.value))
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # GSF_NOALLOC_SCRATCH_BYTES
+
+
+def find_noalloc(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False,
+                 halos=None) -> dict:
+    """``find`` through gsf_find_noalloc: the library's own scratch instead of
+    a workspace (cubes run one after another on the current stream).  Output
+    tensors are still allocated here, by torch, for the caller."""
+    if isinstance(cubes, torch.Tensor):
+        cubes = [cubes]
+    plan = FindPlan(cubes, filters, box, k, want_F=want_F, want_stats=want_stats, halos=halos,
+                    noalloc=True)
+    plan.run()
+    return {"mask": plan.masks, "F": plan.F, "mean": plan.mean, "std": plan.std}
 
 
 def find(cubes, filters, box, k: float, want_F: bool = False, want_stats: bool = False,

@@ -529,7 +529,19 @@ struct DeviceState {
     hipStream_t stream[kSlots];
     hipEvent_t fork;
     hipEvent_t join[kSlots];
+    void *scratch = nullptr;   // this device's copy of `scratch` (gsf_find_noalloc)
 };
+
+// The workspace of gsf_find_noalloc: one gsf_find slot in a library-owned
+// device array, for callers that cannot allocate.  Each device holds its own
+// copy at its own address.  In host code the name `scratch` is a host-side
+// stand-in, not device memory: only the address hipGetSymbolAddress returns
+// for the current device (DeviceState::scratch) is ever passed to kernels.
+// Nothing in it needs clearing: every byte a call reads (the spectral
+// intermediate, F, window sums, shift partials and shifts) is written by that
+// call's kernels first.
+constexpr size_t kScratchBytes = GSF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 std::mutex g_dev_mu;
 std::map<int, DeviceState> g_dev;
@@ -558,6 +570,19 @@ gsf_status init_streams(DeviceState &ds)
                hipEventCreateWithFlags(&ds.join[i], hipEventDisableTiming) == hipSuccess;
     if (!good) return fail(GSF_ERR_DEVICE, "creating the batch streams failed");
     ds.streams_ready = true;
+    return GSF_OK;
+}
+
+// Look up this device's scratch address once (the device must be current).
+gsf_status init_scratch(DeviceState &ds)
+{
+    if (ds.scratch) return GSF_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(GSF_ERR_DEVICE, "looking up the scratch address failed: %s",
+                    hipGetErrorString(e));
+    ds.scratch = p;
     return GSF_OK;
 }
 
@@ -744,7 +769,7 @@ gsf_status gsf_init(void)
     if ((st = current_device(&dev))) return st;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     DeviceState &ds = g_dev[dev];
-    if ((st = init_streams(ds))) return st;
+    if ((st = init_streams(ds)) || (st = init_scratch(ds))) return st;
     return ok();
 }
 
@@ -844,6 +869,45 @@ gsf_status gsf_find(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, 
     }
     return find_enqueue(cubes, ncubes, f, nfilt, b, k, masks, F_out, mean_out, std_out, ws,
                         L, nslots, ss, caller);
+}
+
+gsf_status gsf_find_noalloc(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f,
+                            int32_t nfilt, gsf_box b, double k, uint64_t *const *masks,
+                            void *const *F_out, float *const *mean_out, float *const *std_out,
+                            void *stream)
+{
+    gsf_status st;
+    gsf_dims largest{};
+    if ((st = check_batch(cubes, ncubes, f, nfilt, b, &largest))) return st;
+    if (!std::isfinite(k)) return fail(GSF_ERR_INVALID_ARG, "k must be finite");
+    if (!masks) return fail(GSF_ERR_INVALID_ARG, "masks is NULL");
+    const Layout L = find_layout(cubes, ncubes, f, nfilt, b, largest);
+    const size_t need = slot_ws(L);
+    if (need > kScratchBytes)
+        return fail(GSF_ERR_BUDGET,
+                    "gsf_find_noalloc: this batch needs %zu bytes of scratch, the library "
+                    "holds %zu (GSF_NOALLOC_SCRATCH_BYTES)",
+                    need, kScratchBytes);
+    const hipStream_t caller = (hipStream_t)stream;
+    void *ws = nullptr;
+    {
+        int dev = 0;
+        if ((st = current_device(&dev))) return st;
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        DeviceState &ds = g_dev[dev];
+        if (!ds.scratch) {
+            if (capturing(caller))
+                return fail(GSF_ERR_UNSUPPORTED,
+                            "gsf_find_noalloc: the scratch address is looked up outside "
+                            "captures; call gsf_init() before the capture");
+            if ((st = init_scratch(ds))) return st;
+        }
+        ws = ds.scratch;
+    }
+    if ((st = check_outputs(cubes, ncubes, nfilt, masks, F_out, mean_out, std_out, ws, need)))
+        return st;
+    return find_enqueue(cubes, ncubes, f, nfilt, b, k, masks, F_out, mean_out, std_out, ws, L, 1,
+                        nullptr, caller);
 }
 
 }  // extern "C"

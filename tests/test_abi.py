@@ -223,3 +223,27 @@ def test_find_workspace_counts_merged_filters(L):
     assert one >= 4 * cb and one < 4 * cb + (1 << 20)
     # four cubes of window sums on the generic statistics path (box 128 > 64)
     assert ws([(1, 1)], B.Box(128, 16, 16)) - ws([(1, 1)]) == 2 * cb
+
+
+def test_find_noalloc_validation(L):
+    """gsf_find_noalloc validates like gsf_find and refuses, before any device
+    call, a batch whose one-slot workspace exceeds its scratch."""
+    cubes = (B.Cube * 1)()
+    cubes[0].data = 4096
+    cubes[0].dims = B.Dims(8, 8, 8)
+    filt = (B.Filter * 1)(B.Filter(1, 1, 3))
+    masks = (ctypes.c_void_p * 1)(1 << 20)
+    box = B.Box(4, 4, 4)
+    assert L.gsf_find_noalloc(cubes, 0, filt, 1, box, 4.0, masks, None, None, None, None) == 1
+    assert L.gsf_find_noalloc(cubes, 1, filt, 0, box, 4.0, masks, None, None, None, None) == 1
+    assert L.gsf_find_noalloc(cubes, 1, filt, 1, box, 4.0, None, None, None, None, None) == 1
+    assert L.gsf_find_noalloc(cubes, 1, filt, 1, box, float("inf"), masks, None, None, None,
+                              None) == 1
+    # one FP32 slot with a group of three filters holds T1, three F and two
+    # window-sum cubes: 6 x 48 MiB for 256 x 256 x 192 voxels passes 256 MiB
+    cubes[0].dims = B.Dims(256, 256, 192)
+    filt3 = (B.Filter * 3)(B.Filter(1, 2, 3), B.Filter(2, 2, 3), B.Filter(4, 2, 3))
+    box8 = B.Box(8, 8, 8)
+    assert L.gsf_find_noalloc(cubes, 1, filt3, 3, box8, 4.0, masks, None, None, None,
+                              None) == B.GSF_ERR_BUDGET
+    assert b"GSF_NOALLOC_SCRATCH_BYTES" in L.gsf_last_error()
