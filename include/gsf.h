@@ -248,6 +248,11 @@ typedef struct gsf_tuning {
     int32_t yz_waves;      /* waves per block of the yz window-sum kernel: 0
                               (default: fewest columns walked for the depth), 3, 5
                               or 9 */
+    int32_t pair_spectral; /* 1 (default): two filter groups with different
+                              sigma_z whose spectral radii form a compiled pair
+                              ({3,6}, {3,12}, {6,12}, {6,24}, {12,24}, {3,24})
+                              get both spectral passes from one read of the cube;
+                              0: one spectral pass per group */
 } gsf_tuning;
 
 /* Size class of a cube core: floor(log2(nx*ny*nz)), 0..40; -1 if invalid. */

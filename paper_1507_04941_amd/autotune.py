@@ -33,7 +33,8 @@ import torch
 
 from . import binding as B
 
-DEFAULT = {"merge_sweeps": 1, "merged_shape": 0, "sweep_blocks": 512, "yz_waves": 0}
+DEFAULT = {"merge_sweeps": 1, "merged_shape": 0, "sweep_blocks": 512, "yz_waves": 0,
+           "pair_spectral": 1}
 SWEEP_FORMS = [dict(merge_sweeps=1, merged_shape=0), dict(merge_sweeps=1, merged_shape=1),
                dict(merge_sweeps=1, merged_shape=2), dict(merge_sweeps=0, merged_shape=0)]
 SWEEP_BLOCKS = [256, 512, 1024, 2048]

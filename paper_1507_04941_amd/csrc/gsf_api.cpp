@@ -225,6 +225,8 @@ gsf_status check_tuning(const gsf_tuning *c)
         return fail(GSF_ERR_INVALID_ARG, "sweep_blocks must be in [64, 65536]");
     if (c->yz_waves != 0 && c->yz_waves != 3 && c->yz_waves != 5 && c->yz_waves != 9)
         return fail(GSF_ERR_INVALID_ARG, "yz_waves must be 0, 3, 5 or 9");
+    if (c->pair_spectral != 0 && c->pair_spectral != 1)
+        return fail(GSF_ERR_INVALID_ARG, "pair_spectral must be 0 or 1");
     return GSF_OK;
 }
 
@@ -470,12 +472,15 @@ constexpr size_t kSlotBudget = (size_t)64 << 30;
 constexpr int kMaxMerge = 3;
 
 // One workspace slot, sized for the batch's largest array:
-// [T1][F x nF][statistics cubes x nS][shift partials x nF][shifts x nF].
-// nF is the largest number of filters that share a spectral pass (at most
-// kMaxMerge: larger groups are swept kMaxMerge at a time); nS is 2, or 4
-// when some cube needs the generic statistics path.
+// [T1 x nT][F x nF][statistics cubes x nS][shift partials x nF][shifts x nF].
+// nT is 2 when two spectral-pass groups can share one read of the cube (a
+// compiled radius pair), else 1; nF is the largest number of filters that
+// share a spectral pass (at most kMaxMerge: larger groups are swept
+// kMaxMerge at a time); nS is 2, or 4 when some cube needs the generic
+// statistics path.
 struct Layout {
     gsf_dims largest;
+    int nT;
     int nF;
     int nS;
 };
@@ -485,15 +490,56 @@ bool same_group(const gsf_filter &a, const gsf_filter &b)
     return a.sigma_z == b.sigma_z && a.truncate == b.truncate;
 }
 
+// Spectral-pass groups of a filter bank: filters with equal (sigma_z,
+// truncate), in order of first appearance, each group's members sorted by
+// spatial radius and cut into sweeps of at most kMaxMerge filters.
+// Consecutive groups (0, 1), (2, 3), ... whose spectral radii form a compiled
+// pair are marked to share one read of the cube.
+struct Group {
+    int32_t rep;                                  // a member (its sigma_z, truncate)
+    std::vector<std::vector<int32_t>> sweeps;
+    bool paired_with_next = false;
+};
+
+std::vector<Group> filter_groups(const gsf_filter *f, int32_t nfilt)
+{
+    std::vector<Group> groups;
+    std::vector<char> seen((size_t)nfilt, 0);
+    for (int32_t g = 0; g < nfilt; ++g) {
+        if (seen[g]) continue;
+        std::vector<int32_t> m;
+        for (int32_t j = g; j < nfilt; ++j)
+            if (!seen[j] && same_group(f[g], f[j])) m.push_back(j), seen[j] = 1;
+        std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b2) {
+            return make_taps(f[a].sigma_xy, f[a].truncate).r <
+                   make_taps(f[b2].sigma_xy, f[b2].truncate).r;
+        });
+        Group gr;
+        gr.rep = g;
+        for (size_t i = 0; i < m.size(); i += kMaxMerge)
+            gr.sweeps.emplace_back(m.begin() + i,
+                                   m.begin() + std::min(m.size(), i + (size_t)kMaxMerge));
+        groups.push_back(std::move(gr));
+    }
+    for (size_t i = 0; i + 1 < groups.size(); i += 2) {
+        const int ra = make_taps(f[groups[i].rep].sigma_z, f[groups[i].rep].truncate).r;
+        const int rb = make_taps(f[groups[i + 1].rep].sigma_z, f[groups[i + 1].rep].truncate).r;
+        groups[i].paired_with_next = gsf::zpass_pair(ra, rb) >= 0;
+    }
+    return groups;
+}
+
 Layout find_layout(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, int32_t nfilt,
                    gsf_box b, gsf_dims largest)
 {
-    Layout L{largest, 1, 2};
+    Layout L{largest, 1, 1, 2};
     for (int32_t g = 0; g < nfilt; ++g) {
         int n = 0;
         for (int32_t j = 0; j < nfilt; ++j) n += same_group(f[g], f[j]) ? 1 : 0;
         L.nF = std::max(L.nF, std::min(n, kMaxMerge));
     }
+    for (const Group &g : filter_groups(f, nfilt))
+        if (g.paired_with_next) L.nT = 2;
     for (int32_t c = 0; c < ncubes; ++c) {
         const gsf_dims core{cubes[c].dims.nx - 2 * (int64_t)cubes[c].halo[0],
                             cubes[c].dims.ny - 2 * (int64_t)cubes[c].halo[1],
@@ -505,7 +551,7 @@ Layout find_layout(const gsf_cube *cubes, int32_t ncubes, const gsf_filter *f, i
 
 size_t slot_ws(const Layout &L)
 {
-    return (size_t)(1 + L.nF + L.nS) * cube_bytes(L.largest) + shift_bytes(L.nF);
+    return (size_t)(L.nT + L.nF + L.nS) * cube_bytes(L.largest) + shift_bytes(L.nF);
 }
 
 int find_slots(int32_t ncubes, const Layout &L)
@@ -649,26 +695,7 @@ gsf_status find_enqueue(const gsf_cube *cubes, int32_t ncubes, const gsf_filter 
         slot_of[(size_t)c] = sl;
         load[(size_t)sl] += vox(c);
     }
-    // Spectral-pass groups: filters with equal (sigma_z, truncate), in order
-    // of first appearance, each group's members sorted by spatial radius and
-    // cut into sweeps of at most kMaxMerge filters.
-    std::vector<std::vector<int32_t>> sweeps;
-    {
-        std::vector<char> seen((size_t)nfilt, 0);
-        for (int32_t g = 0; g < nfilt; ++g) {
-            if (seen[g]) continue;
-            std::vector<int32_t> m;
-            for (int32_t j = g; j < nfilt; ++j)
-                if (!seen[j] && same_group(f[g], f[j])) m.push_back(j), seen[j] = 1;
-            std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b2) {
-                return make_taps(f[a].sigma_xy, f[a].truncate).r <
-                       make_taps(f[b2].sigma_xy, f[b2].truncate).r;
-            });
-            for (size_t i = 0; i < m.size(); i += kMaxMerge)
-                sweeps.emplace_back(m.begin() + i,
-                                    m.begin() + std::min(m.size(), i + (size_t)kMaxMerge));
-        }
-    }
+    const std::vector<Group> groups = filter_groups(f, nfilt);
     if (nslots > 1) {
         if (hipEventRecord(ss->fork, caller) != hipSuccess)
             return fail(GSF_ERR_DEVICE, "gsf_find: fork event failed");
@@ -683,9 +710,10 @@ gsf_status find_enqueue(const gsf_cube *cubes, int32_t ncubes, const gsf_filter 
         const int sl = slot_of[(size_t)c];
         const hipStream_t s = nslots > 1 ? ss->stream[sl] : caller;
         char *base = (char *)ws + (size_t)sl * sws;
-        void *T1 = base;                              // FP32
-        char *Fbuf = base + cb;                       // nF cubes
-        const StatsWs w = carve_stats(base + (size_t)(1 + L.nF) * cb, L.largest, L.nS, L.nF);
+        void *T1s[2] = {base, L.nT > 1 ? base + cb : nullptr};   // FP32
+        char *Fbuf = base + (size_t)L.nT * cb;                   // nF cubes
+        const StatsWs w =
+            carve_stats(base + (size_t)(L.nT + L.nF) * cb, L.largest, L.nS, L.nF);
         const gsf_cube &q = cubes[c];
         const gsf_dims core = core_dims(q);
         const gsf::Dims dd = to_dims(core);           // the core: F, statistics, masks
@@ -693,55 +721,65 @@ gsf_status find_enqueue(const gsf_cube *cubes, int32_t ncubes, const gsf_filter 
         const gsf::Store sto = to_store(q.dtype);
         const gsf::Tune tune = tune_for(core, q.dtype);
         gsf::set_active_tune(tune);
-        int32_t last_z = -1;
-        for (const std::vector<int32_t> &sw : sweeps) {
-            const int32_t g = sw[0];
-            // the spectral pass, once per group (consecutive sweeps of one
-            // group share it)
-            if (last_z < 0 || !same_group(f[last_z], f[g])) {
-                const gsf::Taps tz = make_taps(f[g].sigma_z, f[g].truncate);
-                const hipError_t e = gsf::launch_zpass(q.data, T1, sto, dd, h, tz, s);
+        bool have_next = false;                       // T1s[1] holds the next group's pass
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &gr = groups[gi];
+            const gsf::Taps tz = make_taps(f[gr.rep].sigma_z, f[gr.rep].truncate);
+            void *T1 = T1s[0];
+            if (have_next) {
+                T1 = T1s[1];
+                have_next = false;
+            } else {
+                hipError_t e = hipErrorInvalidValue;
+                if (gr.paired_with_next && tune.pair_spectral && L.nT > 1) {
+                    const Group &nx = groups[gi + 1];
+                    const gsf::Taps tz2 = make_taps(f[nx.rep].sigma_z, f[nx.rep].truncate);
+                    e = gsf::launch_zpass_pair(q.data, T1s[0], T1s[1], sto, dd, h, tz, tz2, s);
+                    have_next = e == hipSuccess;
+                }
+                if (e == hipErrorInvalidValue) e = gsf::launch_zpass(q.data, T1, sto, dd, h, tz, s);
                 if (e != hipSuccess) return device_status(e, "gsf_find launch");
-                last_z = g;
             }
-            const int n = (int)sw.size();
-            gsf::Taps txy[kMaxMerge];
-            void *F[kMaxMerge];
-            int r[kMaxMerge];
-            for (int i = 0; i < n; ++i) {
-                const int64_t o = (int64_t)c * nfilt + sw[i];
-                txy[i] = make_taps(f[sw[i]].sigma_xy, f[sw[i]].truncate);
-                r[i] = txy[i].r;
-                F[i] = (F_out && F_out[o]) ? F_out[o] : (void *)(Fbuf + (size_t)i * cb);
+            for (const std::vector<int32_t> &sw : gr.sweeps) {
+                const int n = (int)sw.size();
+                gsf::Taps txy[kMaxMerge];
+                void *F[kMaxMerge];
+                int r[kMaxMerge];
+                for (int i = 0; i < n; ++i) {
+                    const int64_t o = (int64_t)c * nfilt + sw[i];
+                    txy[i] = make_taps(f[sw[i]].sigma_xy, f[sw[i]].truncate);
+                    r[i] = txy[i].r;
+                    F[i] = (F_out && F_out[o]) ? F_out[o] : (void *)(Fbuf + (size_t)i * cb);
+                }
+                const int form = (tune.merge && n >= 2) ? gsf::merged_form(r, n) : -1;
+                int nparts[kMaxMerge] = {0, 0, 0};
+                hipError_t e = hipSuccess;
+                if (form >= 0) {
+                    int np = 0;
+                    e = gsf::launch_yx_merged(form, tune.merged_shape, T1, F, sto, dd, h, txy,
+                                              w.partials, &np, s);
+                    for (int i = 0; i < n; ++i) nparts[i] = np;
+                }
+                if (form < 0 || e == hipErrorInvalidValue) {
+                    e = hipSuccess;
+                    for (int i = 0; i < n && e == hipSuccess; ++i)
+                        e = gsf::launch_yx(T1, F[i], w.w1, sto, dd, h, txy[i],
+                                           w.partials + (size_t)i * gsf::kMaxPartials, &nparts[i], s);
+                }
+                for (int i = 0; i < n && e == hipSuccess; ++i) {
+                    const int64_t o = (int64_t)c * nfilt + sw[i];
+                    double *parts = w.partials + (size_t)i * gsf::kMaxPartials;
+                    double *shift = w.shift + i;
+                    e = nparts[i] > 0
+                            ? gsf::launch_mean_partials(parts, nparts[i], dd.voxels(), shift, s)
+                            : gsf::launch_mean(F[i], sto, dd, parts, shift, s);
+                    if (e == hipSuccess)
+                        e = gsf::launch_stats(F[i], sto, dd, to_box(b), shift, w.w1, w.w2, w.w3,
+                                              w.w4, mean_out ? mean_out[o] : nullptr,
+                                              std_out ? std_out[o] : nullptr, masks[o], k, s);
+                }
+                if (e != hipSuccess) return device_status(e, "gsf_find launch");
             }
-            const int form = (tune.merge && n >= 2) ? gsf::merged_form(r, n) : -1;
-            int nparts[kMaxMerge] = {0, 0, 0};
-            hipError_t e = hipSuccess;
-            if (form >= 0) {
-                int np = 0;
-                e = gsf::launch_yx_merged(form, tune.merged_shape, T1, F, sto, dd, h, txy,
-                                          w.partials, &np, s);
-                for (int i = 0; i < n; ++i) nparts[i] = np;
-            }
-            if (form < 0 || e == hipErrorInvalidValue) {
-                e = hipSuccess;
-                for (int i = 0; i < n && e == hipSuccess; ++i)
-                    e = gsf::launch_yx(T1, F[i], w.w1, sto, dd, h, txy[i],
-                                       w.partials + (size_t)i * gsf::kMaxPartials, &nparts[i], s);
-            }
-            for (int i = 0; i < n && e == hipSuccess; ++i) {
-                const int64_t o = (int64_t)c * nfilt + sw[i];
-                double *parts = w.partials + (size_t)i * gsf::kMaxPartials;
-                double *shift = w.shift + i;
-                e = nparts[i] > 0
-                        ? gsf::launch_mean_partials(parts, nparts[i], dd.voxels(), shift, s)
-                        : gsf::launch_mean(F[i], sto, dd, parts, shift, s);
-                if (e == hipSuccess)
-                    e = gsf::launch_stats(F[i], sto, dd, to_box(b), shift, w.w1, w.w2, w.w3,
-                                          w.w4, mean_out ? mean_out[o] : nullptr,
-                                          std_out ? std_out[o] : nullptr, masks[o], k, s);
-            }
-            if (e != hipSuccess) return device_status(e, "gsf_find launch");
         }
     }
     return GSF_OK;
@@ -790,6 +828,7 @@ gsf_status gsf_tuning_set(int32_t cls, gsf_dtype t, const gsf_tuning *cfg)
     v.merged_shape = cfg->merged_shape;
     v.sweep_blocks = cfg->sweep_blocks;
     v.yz_waves = cfg->yz_waves;
+    v.pair_spectral = cfg->pair_spectral;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int c = 0; c < kSizeClasses; ++c)
         if (cls < 0 || c == cls) g_tune[(int)t][c] = v;
@@ -809,6 +848,7 @@ gsf_status gsf_tuning_get(int32_t cls, gsf_dtype t, gsf_tuning *cfg)
     cfg->merged_shape = v.merged_shape;
     cfg->sweep_blocks = v.sweep_blocks;
     cfg->yz_waves = v.yz_waves;
+    cfg->pair_spectral = v.pair_spectral;
     return ok();
 }
 

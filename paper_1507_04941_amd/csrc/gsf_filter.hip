@@ -168,15 +168,113 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
     }
 }
 
+// Two spectral passes of radii R1 < R2 from one read of the input: the
+// block stages each row with the +-R2 halo, every lane holds the
+// (4 + 2 R2)-wide window, and output k of the radius-R1 pass takes the
+// window's entries R2 - R1 + k .. R2 + R1 + k, the same values in the same
+// tap order as k_zpass_rows<R1>, so both outputs are bit for bit those of
+// the single passes.  Used when two filter groups of one call have
+// different sigma_z (the cube is then read once instead of twice).
+template <int R1, int R2, typename St, bool A>
+__global__ __launch_bounds__(kThreads) void k_zpass2_rows(const St *__restrict__ in,
+                                                          float *__restrict__ out1,
+                                                          float *__restrict__ out2,
+                                                          int64_t nrows, int64_t nz, int64_t NZ,
+                                                          int64_t zoff, Taps t1, Taps t2)
+{
+    static_assert(R1 < R2, "radii ascending");
+    constexpr int R = R2;
+    constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
+    constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
+    constexpr int DR = R2 - R1;
+    constexpr uint32_t SZ = sizeof(St);
+    __shared__ float4 tile4[2][TL / 4];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kZRows;
+    const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
+    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    const int64_t zm = z0 + 4 * tid;
+    const bool mine = zm < nz;
+    const bool load = zm + zoff < NZ;
+    const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
+    const bool halo = tid < 2 * R && zh + zoff >= 0 && zh + zoff < NZ;
+    const int th = tid < R ? tid : kZOut + tid;
+    const uint32_t om = (uint32_t)((zm + zoff) * SZ);
+    const uint32_t oh = halo ? (uint32_t)((zh + zoff) * SZ) : kOOB;
+    const uint32_t os = (uint32_t)(zm * sizeof(float));
+    auto fetch = [&](int64_t r, float4 &m, float &h) {
+        if constexpr (A) {
+            const St *row = in + r * NZ + zoff;
+            m = load ? load4(row + zm) : make_float4(0.f, 0.f, 0.f, 0.f);
+            h = halo ? widen(row[zh]) : 0.0f;
+        } else {
+            const __amdgpu_buffer_rsrc_t rr = buf(in + r * NZ, (uint32_t)(NZ * SZ));
+            m.x = sbuf_ld<St>(rr, om);
+            m.y = sbuf_ld<St>(rr, om + SZ);
+            m.z = sbuf_ld<St>(rr, om + 2 * SZ);
+            m.w = sbuf_ld<St>(rr, om + 3 * SZ);
+            h = sbuf_ld<St>(rr, oh);
+        }
+    };
+    auto put = [&](float *out, int64_t r, const float (&acc)[4]) {
+        if constexpr (A) {
+            if (mine) store4(out + r * nz + zm, acc);
+        } else {
+            const __amdgpu_buffer_rsrc_t ro = buf(out + r * nz, (uint32_t)(nz * sizeof(float)));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) buf_st(ro, acc[k], os + (uint32_t)k * sizeof(float));
+        }
+    };
+    float4 m;
+    float h;
+    fetch(r0, m, h);
+    for (int64_t r = r0; r < r1; ++r) {
+        const int b = (int)((r - r0) & 1);
+        float *tile = reinterpret_cast<float *>(tile4[b]);
+        tile[R + 4 * tid] = m.x;
+        tile[R + 4 * tid + 1] = m.y;
+        tile[R + 4 * tid + 2] = m.z;
+        tile[R + 4 * tid + 3] = m.w;
+        if (tid < 2 * R) tile[th] = h;
+        __syncthreads();
+        if (r + 1 < r1) fetch(r + 1, m, h);
+        float w[4 * NW];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const float4 q = tile4[b][tid + j];
+            w[4 * j] = q.x;
+            w[4 * j + 1] = q.y;
+            w[4 * j + 2] = q.z;
+            w[4 * j + 3] = q.w;
+        }
+        float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int o = 0; o <= 2 * R1; ++o) {
+            const float g = t1.g[o];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a1[k] = fmaf(g, w[DR + k + o], a1[k]);
+        }
+        put(out1, r, a1);
+        float a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int o = 0; o <= 2 * R2; ++o) {
+            const float g = t2.g[o];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a2[k] = fmaf(g, w[k + o], a2[k]);
+        }
+        put(out2, r, a2);
+    }
+}
+
 // With DIV, F holds the numerator N of Eq. 1 on entry and the sweep's
 // result D is not stored: each output becomes N / D (0 where D = 0), read
 // and written in place by the same lane.
 template <int R, int P, int NW, typename St, bool DIV = false>
 __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
-                                                  St *F, int64_t nx, int64_t ny,
-                                                  int64_t nz, int64_t xchunk, Taps t,
-                                                  double *__restrict__ partials, int64_t NX,
-                                                  int64_t NY, int64_t hx, int64_t hy)
+                                                  St *F, int64_t nx64, int64_t ny64,
+                                                  int64_t nz64, int64_t xchunk, Taps t,
+                                                  double *__restrict__ partials, int64_t NX64,
+                                                  int64_t NY64, int64_t hx64, int64_t hy64)
 {
     constexpr int L = 2 * R + 1;
     constexpr int TY = NW * P;            // output rows of the block
@@ -195,30 +293,36 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
     __shared__ float stage[S][TR][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int64_t z = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t yb = (int64_t)blockIdx.y * TY;                   // first output row of the block
-    const int64_t y0 = yb + wave * P;                              // this wave's first row
-    const int64_t xa = (int64_t)blockIdx.z * xchunk;
-    const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
+    __builtin_assume(wave >= 0 && wave < NW);
+    // 32-bit plane, row and in-plane indices (a plane holds < 2^28 voxels):
+    // the x loop's bounds and tests stay scalar, which keeps the uniform
+    // state (taps included) in scalar registers without spills.
+    const int z = (int)blockIdx.x * 64 + lane;
+    const int yb = (int)blockIdx.y * TY;                    // first output row of the block
+    const int y0 = yb + wave * P;                           // this wave's first row
+    const int nx = (int)nx64, ny = (int)ny64, nz = (int)nz64, NX = (int)NX64;
+    const int xa = (int)blockIdx.z * (int)xchunk;
+    const int xb = xa + (int)xchunk < nx ? xa + (int)xchunk : nx;
+    const int hx = (int)hx64;
     const bool zl = z < nz;
     // T1 is NX x NY rows of nz (core z); F is the nx x ny x nz core, whose
     // (x, y) reads T1 at (x + hx, y + hy)
-    constexpr int64_t SZ = sizeof(St);
-    constexpr int64_t TSZ = sizeof(float);                        // T1 is FP32
-    const int64_t tplane = NY * nz;
-    const uint32_t tplane_b = (uint32_t)(tplane * TSZ);
-    const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * SZ);
-    const uint32_t row_b = (uint32_t)(nz * SZ);
+    constexpr uint32_t SZ = sizeof(St);
+    constexpr uint32_t TSZ = sizeof(float);                 // T1 is FP32
+    const uint32_t tplane = (uint32_t)NY64 * (uint32_t)nz;
+    const uint32_t tplane_b = tplane * TSZ;
+    const uint32_t plane = (uint32_t)ny * (uint32_t)nz;
+    const uint32_t plane_b = plane * SZ;
+    const uint32_t row_b = (uint32_t)nz * SZ;
     // rows w, w + NW, ... of the block's TR-row window are this wave's to load;
     // offsets wrap for rows above the array and read 0 through the range check
     uint32_t ldo[LW];
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
         const int tr = wave + i * NW;
-        ldo[i] = tr < TR ? (uint32_t)(((yb + hy - R + tr) * nz + z) * TSZ) : kOOB;
+        ldo[i] = tr < TR ? (uint32_t)((yb + (int)hy64 - R + tr) * nz + z) * TSZ : kOOB;
     }
-    const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * SZ) : kOOB;
+    const uint32_t st0 = zl ? (uint32_t)(y0 * nz + z) * SZ : kOOB;
 
     float acc[P][L];
 #pragma unroll
@@ -227,14 +331,15 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
         for (int m = 0; m < L; ++m) acc[q][m] = 0.0f;
 
     double fsum = 0.0;                                       // this lane's share of sum(F)
-    const int64_t p_start = xa - R;
-    const int64_t p_end = xb - 1 + R;                       // inclusive
+    const int p_start = xa - R;
+    const int p_end = xb - 1 + R;                            // inclusive
 
     // a plane outside [0, nx) gets an empty range, so its rows read 0
-    auto load_plane = [&](int64_t xq, float (&r)[LW]) {
-        const int64_t xt = xq + hx;                          // T1 plane of core plane xq
-        const bool in = xt >= 0 && xt < NX;
-        const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xt : 0) * tplane, in ? tplane_b : 0u);
+    auto load_plane = [&](int xq, float (&r)[LW]) {
+        const int xt = xq + hx;                              // T1 plane of core plane xq
+        const bool in = (unsigned)xt < (unsigned)NX;
+        const __amdgpu_buffer_rsrc_t rt =
+            buf(T + (size_t)(in ? xt : 0) * tplane, in ? tplane_b : 0u);
 #pragma unroll
         for (int i = 0; i < LW; ++i) r[i] = buf_ld(rt, ldo[i]);
     };
@@ -255,24 +360,24 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
     // them defeats the load pipelining.)
     float rq[D][LW];
     load_plane(p_start, rq[0]);
-    store_stage((int)(p_start & (S - 1)), rq[0]);
+    store_stage(p_start & (S - 1), rq[0]);
 #pragma unroll
     for (int k = 0; k < D; ++k) load_plane(p_start + 1 + k, rq[k]);
 
 #pragma nounroll
-    for (int64_t p0 = p_start; p0 <= p_end; p0 += L) {
+    for (int p0 = p_start; p0 <= p_end; p0 += L) {
 #pragma unroll
         for (int j = 0; j < L; ++j) {
             // Planes outside [0, nx) read 0.
-            const int64_t xp = p0 + j;                       // (xp - p_start) mod L == j
+            const int xp = p0 + j;                           // (xp - p_start) mod L == j
             __syncthreads();
-            store_stage((int)((xp + 1) & (S - 1)), rq[0]);   // plane xp+1
+            store_stage((xp + 1) & (S - 1), rq[0]);          // plane xp+1
 #pragma unroll
             for (int k = 0; k + 1 < D; ++k)
 #pragma unroll
                 for (int i = 0; i < LW; ++i) rq[k][i] = rq[k + 1][i];
             load_plane(xp + D + 1, rq[D - 1]);               // plane xp+D+1
-            const int sx = (int)(xp & (S - 1));              // stage of plane xp
+            const int sx = xp & (S - 1);                     // stage of plane xp
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 float t2 = 0.0f;
@@ -285,9 +390,9 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
                 }
             }
             const int slot_o = (j + R + 1) % L;
-            const int64_t xo = xp - R;
+            const int xo = xp - R;
             if (xo >= xa && xo < xb) {
-                const __amdgpu_buffer_rsrc_t rf = buf(F + xo * plane, plane_b);
+                const __amdgpu_buffer_rsrc_t rf = buf(F + (size_t)xo * plane, plane_b);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     if constexpr (DIV) {
@@ -363,6 +468,42 @@ hipError_t zpass_r(const void *in, void *out, Dims d, const Halo &h, const Taps 
                    hipStream_t s)
 {
     return zpass_impl<R, St, false>(in, out, d, h, tz, s, nullptr);
+}
+
+// Radius pairs with a compiled two-pass spectral kernel (ascending).
+constexpr int kZPairs = 6;
+constexpr int kZPair[kZPairs][2] = {{3, 6}, {3, 12}, {6, 12}, {6, 24}, {12, 24}, {3, 24}};
+
+template <int R1, int R2, typename St>
+hipError_t zpass2_impl(const void *in_, void *o1, void *o2, Dims d, const Halo &h,
+                       const Taps &t1, const Taps &t2, hipStream_t s)
+{
+    const St *in = (const St *)in_;
+    const int64_t rows = h.NX * h.NY;
+    const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
+    static const std::string name = "k_zpass2_r<" + std::to_string(R1) + "," +
+                                    std::to_string(R2) + store_suffix<St>() + ">";
+    prof::Scope scope(name.c_str(), s);
+    const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
+    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0)
+        hipLaunchKernelGGL((k_zpass2_rows<R1, R2, St, true>), grid, dim3(kThreads), 0, s, in,
+                           (float *)o1, (float *)o2, rows, d.nz, h.NZ, (int64_t)h.hz, t1, t2);
+    else
+        hipLaunchKernelGGL((k_zpass2_rows<R1, R2, St, false>), grid, dim3(kThreads), 0, s, in,
+                           (float *)o1, (float *)o2, rows, d.nz, h.NZ, (int64_t)h.hz, t1, t2);
+    return hipGetLastError();
+}
+
+using Z2Fn = hipError_t (*)(const void *, void *, void *, Dims, const Halo &, const Taps &,
+                            const Taps &, hipStream_t);
+
+template <typename St>
+const Z2Fn *z2tab()
+{
+    static const Z2Fn tab[kZPairs] = {&zpass2_impl<3, 6, St>,   &zpass2_impl<3, 12, St>,
+                                      &zpass2_impl<6, 12, St>,  &zpass2_impl<6, 24, St>,
+                                      &zpass2_impl<12, 24, St>, &zpass2_impl<3, 24, St>};
+    return tab;
 }
 
 template <int R, int P, int NW, typename St, bool DIV = false>
@@ -474,6 +615,30 @@ hipError_t launch_yx_div_fast(const float *T1, float *F, Dims d, const Taps &txy
     if (!yx_fast(txy.r, d)) return hipErrorInvalidValue;
     return yxdivtab_of(std::make_integer_sequence<int, kMaxFastRxy>{})[txy.r](
         T1, F, d, no_halo(d), txy, nullptr, nullptr, s);
+}
+
+int zpass_pair(int ra, int rb)
+{
+    const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+    for (int i = 0; i < kZPairs; ++i)
+        if (kZPair[i][0] == lo && kZPair[i][1] == hi) return i;
+    return -1;
+}
+
+hipError_t launch_zpass_pair(const void *in, void *Ta, void *Tb, Store st, Dims d, const Halo &h,
+                             const Taps &ta, const Taps &tb, hipStream_t s)
+{
+    const int i = zpass_pair(ta.r, tb.r);
+    if (i < 0) return hipErrorInvalidValue;
+    // the kernel takes the smaller radius first
+    const bool sw = ta.r > tb.r;
+    void *o1 = sw ? Tb : Ta, *o2 = sw ? Ta : Tb;
+    const Taps &t1 = sw ? tb : ta, &t2 = sw ? ta : tb;
+    switch (st) {
+    case Store::F16: return z2tab<_Float16>()[i](in, o1, o2, d, h, t1, t2, s);
+    case Store::BF16: return z2tab<__bf16>()[i](in, o1, o2, d, h, t1, t2, s);
+    default: return z2tab<float>()[i](in, o1, o2, d, h, t1, t2, s);
+    }
 }
 
 int merged_form(const int *r, int nf)

@@ -60,11 +60,14 @@ struct Box {
 //                 chunks (each chunk re-reads 2r planes)
 //   yz_waves      waves per block of the yz window kernel (3, 5 or 9; 0: the
 //                 one that walks the fewest columns for the cube's depth)
+//   pair_spectral 1: two spectral-pass groups with a compiled radius pair
+//                 share one read of the cube; 0: one spectral pass each
 struct Tune {
     int merge = 1;
     int merged_shape = 0;
     int sweep_blocks = 512;
     int yz_waves = 0;
+    int pair_spectral = 1;
 };
 
 // The configuration of the call being enqueued on this thread: the API layer
@@ -102,6 +105,13 @@ bool plane_fits(Dims d);
 bool yx_fast(int rxy, Dims d);
 hipError_t launch_zpass_fast(const void *in, void *T1, Store st, Dims d, const Halo &h,
                              const Taps &tz, hipStream_t s);
+// Two spectral passes of different radii from one read of the input (Ta with
+// taps ta, Tb with tb); zpass_pair(ra, rb) is the compiled pair's index or
+// -1, and launch_zpass_pair returns hipErrorInvalidValue for other radii.
+// Bit for bit the results of two launch_zpass_fast calls.
+int zpass_pair(int ra, int rb);
+hipError_t launch_zpass_pair(const void *in, void *Ta, void *Tb, Store st, Dims d, const Halo &h,
+                             const Taps &ta, const Taps &tb, hipStream_t s);
 hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo &h,
                           const Taps &txy, double *partials, int *nparts, hipStream_t s);
 // Merged spatial sweeps: one kernel applies the spatial passes of 2 or 3

@@ -68,10 +68,10 @@ __host__ __device__ constexpr int sym(int o, int R) { return o <= R ? o : 2 * R 
 
 template <int P, int NW, typename St, int R0, int R1, int R2>
 __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St *F0, St *F1,
-                                                 St *F2, int64_t nx, int64_t ny, int64_t nz,
-                                                 int64_t xchunk, TapsM t,
-                                                 double *__restrict__ partials, int64_t NX,
-                                                 int64_t NY, int64_t hx, int64_t hy)
+                                                 St *F2, int64_t nx64, int64_t ny64,
+                                                 int64_t nz64, int64_t xchunk, TapsM t,
+                                                 double *__restrict__ partials, int64_t NX64,
+                                                 int64_t NY64, int64_t hx64, int64_t hy64)
 {
     constexpr int NF = R2 > 0 ? 3 : 2;
     constexpr int RM = cmax<cmax<R0, R1>(), R2>();
@@ -86,27 +86,33 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
     __shared__ float stage[S][TR][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t z = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t yb = (int64_t)blockIdx.y * TY;
-    const int64_t y0 = yb + wave * P;
-    const int64_t xa = (int64_t)blockIdx.z * xchunk;
-    const int64_t xb = xa + xchunk < nx ? xa + xchunk : nx;
+    __builtin_assume(wave >= 0 && wave < NW);
+    // Plane indices are 32-bit (planes, rows and in-plane offsets all fit):
+    // the x loop's bounds and tests then stay in scalar registers and scalar
+    // compares, and leave room for the taps, which are also uniform.
+    const int z = (int)blockIdx.x * 64 + lane;
+    const int yb = (int)blockIdx.y * TY;
+    const int y0 = yb + wave * P;
+    const int nx = (int)nx64, ny = (int)ny64, nz = (int)nz64, NX = (int)NX64;
+    const int xa = (int)blockIdx.z * (int)xchunk;
+    const int xb = xa + (int)xchunk < nx ? xa + (int)xchunk : nx;
+    const int hx = (int)hx64;
     const bool zl = z < nz;
-    constexpr int64_t SZ = sizeof(St);
-    constexpr int64_t TSZ = sizeof(float);
-    const int64_t tplane = NY * nz;
-    const uint32_t tplane_b = (uint32_t)(tplane * TSZ);
-    const int64_t plane = ny * nz;
-    const uint32_t plane_b = (uint32_t)(plane * SZ);
-    const uint32_t row_b = (uint32_t)(nz * SZ);
+    constexpr uint32_t SZ = sizeof(St);
+    constexpr uint32_t TSZ = sizeof(float);
+    const uint32_t tplane = (uint32_t)NY64 * (uint32_t)nz;         // < 2^28 voxels
+    const uint32_t tplane_b = tplane * TSZ;
+    const uint32_t plane = (uint32_t)ny * (uint32_t)nz;
+    const uint32_t plane_b = plane * SZ;
+    const uint32_t row_b = (uint32_t)nz * SZ;
     St *const Fs[3] = {F0, F1, F2};
     uint32_t ldo[LW];
 #pragma unroll
     for (int i = 0; i < LW; ++i) {
         const int tr = wave + i * NW;
-        ldo[i] = tr < TR ? (uint32_t)(((yb + hy - RM + tr) * nz + z) * TSZ) : kOOB;
+        ldo[i] = tr < TR ? (uint32_t)((yb + (int)hy64 - RM + tr) * nz + z) * TSZ : kOOB;
     }
-    const uint32_t st0 = zl ? (uint32_t)((y0 * nz + z) * SZ) : kOOB;
+    const uint32_t st0 = zl ? (uint32_t)(y0 * nz + z) * SZ : kOOB;
 
     float acc[3][P][L];
 #pragma unroll
@@ -116,13 +122,14 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
 #pragma unroll
             for (int m = 0; m < L; ++m) acc[f][q][m] = 0.0f;
     double fsum[3] = {0.0, 0.0, 0.0};
-    const int64_t p_start = xa - RM;
-    const int64_t p_end = xb - 1 + RM;
+    const int p_start = xa - RM;
+    const int p_end = xb - 1 + RM;
 
-    auto load_plane = [&](int64_t xq, float (&r)[LW]) {
-        const int64_t xt = xq + hx;
-        const bool in = xt >= 0 && xt < NX;
-        const __amdgpu_buffer_rsrc_t rt = buf(T + (in ? xt : 0) * tplane, in ? tplane_b : 0u);
+    auto load_plane = [&](int xq, float (&r)[LW]) {
+        const int xt = xq + hx;
+        const bool in = (unsigned)xt < (unsigned)NX;
+        const __amdgpu_buffer_rsrc_t rt =
+            buf(T + (size_t)(in ? xt : 0) * tplane, in ? tplane_b : 0u);
 #pragma unroll
         for (int i = 0; i < LW; ++i) r[i] = buf_ld(rt, ldo[i]);
     };
@@ -135,23 +142,23 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
     };
     float rq[D][LW];
     load_plane(p_start, rq[0]);
-    store_stage((int)(p_start & (S - 1)), rq[0]);
+    store_stage(p_start & (S - 1), rq[0]);
 #pragma unroll
     for (int k = 0; k < D; ++k) load_plane(p_start + 1 + k, rq[k]);
 
 #pragma nounroll
-    for (int64_t p0 = p_start; p0 <= p_end; p0 += L) {
+    for (int p0 = p_start; p0 <= p_end; p0 += L) {
 #pragma unroll
         for (int j = 0; j < L; ++j) {
-            const int64_t xp = p0 + j;
+            const int xp = p0 + j;
             __syncthreads();
-            store_stage((int)((xp + 1) & (S - 1)), rq[0]);
+            store_stage((xp + 1) & (S - 1), rq[0]);
 #pragma unroll
             for (int k = 0; k + 1 < D; ++k)
 #pragma unroll
                 for (int i = 0; i < LW; ++i) rq[k][i] = rq[k + 1][i];
             load_plane(xp + D + 1, rq[D - 1]);
-            const int sx = (int)(xp & (S - 1));
+            const int sx = xp & (S - 1);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const int R = Rs[f];
@@ -169,9 +176,9 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
                     }
                 }
                 const int slot_o = (j - R + L) % L;
-                const int64_t xo = xp - R;
+                const int xo = xp - R;
                 if (xo >= xa && xo < xb) {
-                    const __amdgpu_buffer_rsrc_t rf = buf(Fs[f] + xo * plane, plane_b);
+                    const __amdgpu_buffer_rsrc_t rf = buf(Fs[f] + (size_t)xo * plane, plane_b);
 #pragma unroll
                     for (int q = 0; q < P; ++q) {
                         const float v = widen(narrow<St>(acc[f][q][slot_o]));

@@ -173,22 +173,25 @@ def test_find_validation(L):
 
 
 def test_tuning_table_validation(L):
-    t = B.Tuning(1, 0, 512, 0)
+    t = B.Tuning(1, 0, 512, 0, 1)
     assert L.gsf_tuning_set(-1, 0, ctypes.byref(t)) == 0
-    for bad in (B.Tuning(2, 0, 512, 0), B.Tuning(1, 3, 512, 0), B.Tuning(1, -1, 512, 0),
-                B.Tuning(1, 0, 63, 0), B.Tuning(1, 0, 70000, 0), B.Tuning(1, 0, 512, 4)):
+    for bad in (B.Tuning(2, 0, 512, 0, 1), B.Tuning(1, 3, 512, 0, 1), B.Tuning(1, -1, 512, 0, 1),
+                B.Tuning(1, 0, 63, 0, 1), B.Tuning(1, 0, 70000, 0, 1), B.Tuning(1, 0, 512, 4, 1),
+                B.Tuning(1, 0, 512, 0, 2)):
         assert L.gsf_tuning_set(-1, 0, ctypes.byref(bad)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(41, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(-2, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(3, 7, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(3, 0, None) == B.GSF_ERR_INVALID_ARG
-    t2 = B.Tuning(0, 2, 4096, 5)
+    t2 = B.Tuning(0, 2, 4096, 5, 0)
     assert L.gsf_tuning_set(20, 1, ctypes.byref(t2)) == 0
     got = B.Tuning()
     assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
-    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves) == (0, 2, 4096, 5)
+    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves,
+            got.pair_spectral) == (0, 2, 4096, 5, 0)
     assert L.gsf_tuning_get(20, 0, ctypes.byref(got)) == 0
-    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves) == (1, 0, 512, 0)
+    assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves,
+            got.pair_spectral) == (1, 0, 512, 0, 1)
     assert L.gsf_tuning_get(-1, 0, ctypes.byref(got)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_reset() == 0
     assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
@@ -216,11 +219,18 @@ def test_find_workspace_counts_merged_filters(L):
         assert L.gsf_find_workspace_size(cubes, 1, filt, len(filters), box, ctypes.byref(n)) == 0
         return n.value
 
-    one = ws([(1, 1), (2, 2), (2, 4)])
+    parts = ((1 << 16) * 8 + 255) // 256 * 256
+    single = ws([(1, 1)])
     three = ws([(1, 2), (2, 2), (4, 2)])
-    assert three - one == 2 * cb + 2 * (((1 << 16) * 8 + 255) // 256 * 256)
+    assert three - single == 2 * cb + 2 * parts
     # T1 + F + two window-sum cubes (+ shift partials) for the fast statistics
-    assert one >= 4 * cb and one < 4 * cb + (1 << 20)
+    assert single >= 4 * cb and single < 4 * cb + (1 << 20)
+    # spectral radii 3 and 6 form a compiled pair: the first two groups share
+    # one read of the cube into two T1 buffers (the third group reuses the first)
+    paired = ws([(1, 1), (2, 2), (2, 4)])
+    assert paired - single == cb
+    # radii 3 and 15 (sigma_z 5) have no compiled pair: one T1
+    assert ws([(1, 1), (1, 5)]) == single
     # four cubes of window sums on the generic statistics path (box 128 > 64)
     assert ws([(1, 1)], B.Box(128, 16, 16)) - ws([(1, 1)]) == 2 * cb
 

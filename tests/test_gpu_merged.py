@@ -1,8 +1,10 @@
-"""Merged spatial sweeps and launch tunings on the GPU.  The filters of a
-group that shares one spectral pass go through one merged sweep where a form
-is compiled; its F is bit for bit the single-filter sweep's (gsf_filter3d),
-for every block shape and x split, with halos and 16-bit storage.  Every
-tuning gives results that match the FP64 oracle."""
+"""Merged spatial sweeps, paired spectral passes and launch tunings on the
+GPU.  The filters of a group that shares one spectral pass go through one
+merged sweep where a form is compiled, and two groups whose spectral radii
+form a compiled pair get both passes from one read of the cube; F is bit for
+bit the single-filter path's (gsf_filter3d), for every block shape and x
+split, with halos and 16-bit storage.  Every tuning gives results that match
+the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -23,10 +25,13 @@ BANKS = {
     "six": [(1.0, 2.0), (1.0, 8.0), (2.0, 2.0), (2.0, 8.0), (4.0, 2.0), (4.0, 8.0)],
     "pairs": [(2.0, 3.0), (1.0, 3.0), (4.0, 1.5), (1.0, 1.5), (4.0, 5.0), (2.0, 5.0)],
     "four": [(4.0, 2.0), (1.0, 2.0), (1.5, 2.0), (2.0, 2.0)],
+    # spectral radii 3 and 6 share one read of the cube (the paired spectral
+    # pass); radius 12 then has its own pass
+    "cfg0": [(1.0, 1.0), (2.0, 2.0), (2.0, 4.0)],
 }
 TUNINGS = [dict(merged_shape=0), dict(merged_shape=1), dict(merged_shape=2),
            dict(merged_shape=0, sweep_blocks=64), dict(merged_shape=1, sweep_blocks=4096),
-           dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5)]
+           dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5), dict(pair_spectral=0)]
 
 
 @pytest.fixture(autouse=True)
