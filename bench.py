@@ -352,6 +352,27 @@ def errors16(B, cube32, name, w) -> dict:
     return {"against": "the FP32 path on the same cube", "unit": "local std", "filters": per}
 
 
+def tune_for(cubes, w, halos=None) -> dict:
+    """Autotune the library's launch configurations for one workload (per size
+    class of its cores, installed into the library's table for the timed runs
+    that follow) and summarise the choice: per class the chosen entry's
+    non-default fields and its time against the starting entry's."""
+    from paper_1507_04941_amd import autotune
+    t0 = time.perf_counter()
+    cache = autotune.tune(cubes, w.filters, w.box, w.k, halos=halos, steps=2, reps=3)
+    out = {}
+    for key, e in sorted(cache.items()):
+        cls = key.split("|")[1]
+        first = e["trials"][0]
+        out[cls] = {"config": {k: v for k, v in e["config"].items()
+                               if v != autotune.DEFAULT.get(k)},
+                    "ms": e["ms"], "start_ms": first["ms"], "trials": len(e["trials"]),
+                    "cubes": e.get("cubes", 1)}
+    dt = time.perf_counter() - t0
+    print(f"# tuned {len(out)} size class(es) in {dt:.1f} s", file=sys.stderr, flush=True)
+    return {"seconds": round(dt, 1), "classes": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +392,9 @@ def main() -> int:
                     help="requests of the serving run (Poisson, 200/s); 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default launch configurations instead of "
+                         "autotuning them first")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -401,6 +425,9 @@ def main() -> int:
     plan = B.FindPlan([cube], w.filters, w.box, w.k)
     V = w.voxels
     nf = len(w.filters)
+    tuning = {}
+    if not args.no_tune:
+        tuning["cube_f32"] = tune_for([cube], w)
     for _ in range(args.warmup):
         plan.run()
     torch.cuda.synchronize()
@@ -440,6 +467,8 @@ def main() -> int:
     if not args.no_storage16:
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
             c16 = cube.to(dt)
+            if not args.no_tune:
+                tuning[f"cube_{name}"] = tune_for([c16], w)
             p16 = B.FindPlan([c16], w.filters, w.box, w.k)
             for _ in range(args.warmup):
                 p16.run()
@@ -501,6 +530,8 @@ def main() -> int:
                  "unit": "GVoxel-filters/s"}
         for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
             cubes = [torch.from_numpy(h).to(dev).to(dt) for h in host]
+            if not args.no_tune:
+                tuning[f"batch_{name}"] = tune_for(cubes, bw, halos=bw.halo)
             pb = B.FindPlan(cubes, bw.filters, bw.box, bw.k, halos=bw.halo)
             for _ in range(args.warmup):
                 pb.run()
@@ -574,6 +605,7 @@ def main() -> int:
         "batch": batch,
         "weighted": weighted,
         "serving": serving,
+        "tuning": tuning or None,
     }
     print(json.dumps(line), flush=True)
     return 0

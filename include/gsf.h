@@ -242,7 +242,8 @@ typedef struct gsf_tuning {
                               sweep where a form is compiled (spatial radii
                               {3,6,12}, {3,6}, {3,12}, {6,12}); 0: one sweep each */
     int32_t merged_shape;  /* merged-sweep block: 0 (default) 1 row per lane x 8
-                              waves, 1: 2 rows x 8 waves, 2: 1 row x 16 waves */
+                              waves, 1: 2 rows x 8 waves, 2: 1 row x 16 waves,
+                              3: 2 rows x 4 waves */
     int32_t sweep_blocks;  /* blocks a spatial sweep aims for before it splits x
                               into chunks, 64..65536 (default 512) */
     int32_t yz_waves;      /* waves per block of the yz window-sum kernel: 0
@@ -268,7 +269,8 @@ gsf_status gsf_tuning_set(int32_t size_class, gsf_dtype dtype, const gsf_tuning 
 /* The entry of size class `size_class` (0..40) and `dtype`. */
 gsf_status gsf_tuning_get(int32_t size_class, gsf_dtype dtype, gsf_tuning *cfg);
 
-/* Every entry back to the defaults. */
+/* Every entry back to the defaults (the values above, except merged_shape 2
+ * for FP32 cores of 2^26 voxels or more). */
 gsf_status gsf_tuning_reset(void);
 
 /* ---- Kernel timing (measurement aid) ---- */

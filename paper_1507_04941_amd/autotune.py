@@ -36,7 +36,8 @@ from . import binding as B
 DEFAULT = {"merge_sweeps": 1, "merged_shape": 0, "sweep_blocks": 512, "yz_waves": 0,
            "pair_spectral": 1}
 SWEEP_FORMS = [dict(merge_sweeps=1, merged_shape=0), dict(merge_sweeps=1, merged_shape=1),
-               dict(merge_sweeps=1, merged_shape=2), dict(merge_sweeps=0, merged_shape=0)]
+               dict(merge_sweeps=1, merged_shape=2), dict(merge_sweeps=1, merged_shape=3),
+               dict(merge_sweeps=0, merged_shape=0)]
 SWEEP_BLOCKS = [256, 512, 1024, 2048]
 YZ_WAVES = [0, 3, 5, 9]
 _DT_NAME = {torch.float32: "f32", torch.float16: "f16", torch.bfloat16: "bf16"}
@@ -110,9 +111,9 @@ def _time_ms(plan, steps: int, reps: int) -> float:
 
 
 def _tune_class(plan, cls: int, dtype, steps: int, reps: int, min_gain: float, log) -> dict:
-    """Coordinate descent for one size class; the other classes keep their
-    current entries.  Returns {"config": ..., "ms": ..., "trials": [...]}."""
-    best = dict(DEFAULT)
+    """Coordinate descent for one size class from its current entry; the other
+    classes keep theirs.  Returns {"config": ..., "ms": ..., "trials": [...]}."""
+    best = B.tuning_get(cls, dtype)
     trials = []
 
     def measure(cfg):

@@ -198,7 +198,29 @@ constexpr int kSizeClasses = 41;   // floor(log2(voxels)) of a core, 0 .. 40
 
 thread_local gsf::Tune t_active;
 std::mutex g_tune_mu;
-gsf::Tune g_tune[3][kSizeClasses];
+
+// Default entry of a storage type and size class: the measured best on the
+// 512x512x1024 cube with the six-filter bank (FP32: the merged sweep's
+// 1-row x 16-wave block, 1.21 against 1.30 ms for 1 x 8; 16-bit: 1 x 8, 1.11
+// against 1.15 ms) for cores of 2^26 voxels and more; 1 x 8 below.
+gsf::Tune default_tune(int t, int cls)
+{
+    gsf::Tune v;
+    if (t == (int)GSF_F32 && cls >= 26) v.merged_shape = 2;
+    return v;
+}
+
+struct TuneTable {
+    gsf::Tune e[3][kSizeClasses];
+    TuneTable() { reset(); }
+    void reset()
+    {
+        for (int t = 0; t < 3; ++t)
+            for (int c = 0; c < kSizeClasses; ++c) e[t][c] = default_tune(t, c);
+    }
+};
+TuneTable g_table;
+gsf::Tune (&g_tune)[3][kSizeClasses] = g_table.e;
 
 int size_class(gsf_dims d)
 {
@@ -855,8 +877,7 @@ gsf_status gsf_tuning_get(int32_t cls, gsf_dtype t, gsf_tuning *cfg)
 gsf_status gsf_tuning_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (auto &row : g_tune)
-        for (auto &v : row) v = gsf::Tune{};
+    g_table.reset();
     return ok();
 }
 

@@ -118,8 +118,8 @@ hipError_t launch_yx_fast(const void *T1, void *F, Store st, Dims d, const Halo 
 // filters that share T1 (equal sigma_z).  merged_form(r, nf) returns the
 // index of the compiled form for radii r[0] < r[1] (< r[2]), or -1.
 // launch_yx_merged writes F[i] for taps txy[i] (radius r[i]) with block
-// shape `shape` (0: 2 rows per lane, 8 waves; 1: 1 row, 8 waves; 2: 2 rows,
-// 4 waves); its shift partials go to partials + i * kMaxPartials (*nparts
+// shape `shape` (an index of kMergedShape: rows per lane and waves per
+// block); its shift partials go to partials + i * kMaxPartials (*nparts
 // blocks each, 0 if not written).  hipErrorInvalidValue when the form does
 // not fit the call.
 constexpr int kMaxMergedR = 12;

@@ -20,8 +20,10 @@ using MergedFn = hipError_t (*)(const void *, void *const *, Dims, const Halo &,
 
 // Compiled radius sets (ascending) and block shapes (rows per lane P, waves
 // per block NW).  Measured register use (FP32, radii 3, 6, 12): P2 NW8 164
-// VGPRs (3 waves per SIMD, one block per CU), P1 NW8 108 VGPRs (two blocks
-// per CU), P1 NW16 108 VGPRs (one block of 16 waves).
+// VGPRs (3 waves per SIMD, one block per CU), P1 NW8 103 VGPRs (two blocks
+// per CU), P1 NW16 103 VGPRs (one block of 16 waves), P2 NW4 (three blocks
+// of 4 waves per CU: half the LDS reads per output of P1, the same T1 rows
+// per plane as P1 NW8).
 struct MergedRadii {
     int nf;
     int r[3];
@@ -29,8 +31,8 @@ struct MergedRadii {
 constexpr int kMergedForms = 4;
 constexpr MergedRadii kMergedRadii[kMergedForms] = {
     {3, {3, 6, 12}}, {2, {3, 6, 0}}, {2, {3, 12, 0}}, {2, {6, 12, 0}}};
-constexpr int kMergedShapes = 3;
-constexpr int kMergedShape[kMergedShapes][2] = {{1, 8}, {2, 8}, {1, 16}};
+constexpr int kMergedShapes = 4;
+constexpr int kMergedShape[kMergedShapes][2] = {{1, 8}, {2, 8}, {1, 16}, {2, 4}};
 
 // Launcher of compiled form `form` with block shape `shape` for each storage
 // type (defined in gsf_merged_f32.hip, _f16.hip, _bf16.hip).
@@ -255,7 +257,8 @@ constexpr std::array<MergedFn, kMergedShapes> shapes_of()
 {
     return {&yxm<kMergedShape[0][0], kMergedShape[0][1], St, R0, R1, R2>,
             &yxm<kMergedShape[1][0], kMergedShape[1][1], St, R0, R1, R2>,
-            &yxm<kMergedShape[2][0], kMergedShape[2][1], St, R0, R1, R2>};
+            &yxm<kMergedShape[2][0], kMergedShape[2][1], St, R0, R1, R2>,
+            &yxm<kMergedShape[3][0], kMergedShape[3][1], St, R0, R1, R2>};
 }
 
 template <typename St>

@@ -175,7 +175,7 @@ def test_find_validation(L):
 def test_tuning_table_validation(L):
     t = B.Tuning(1, 0, 512, 0, 1)
     assert L.gsf_tuning_set(-1, 0, ctypes.byref(t)) == 0
-    for bad in (B.Tuning(2, 0, 512, 0, 1), B.Tuning(1, 3, 512, 0, 1), B.Tuning(1, -1, 512, 0, 1),
+    for bad in (B.Tuning(2, 0, 512, 0, 1), B.Tuning(1, 4, 512, 0, 1), B.Tuning(1, -1, 512, 0, 1),
                 B.Tuning(1, 0, 63, 0, 1), B.Tuning(1, 0, 70000, 0, 1), B.Tuning(1, 0, 512, 4, 1),
                 B.Tuning(1, 0, 512, 0, 2)):
         assert L.gsf_tuning_set(-1, 0, ctypes.byref(bad)) == B.GSF_ERR_INVALID_ARG
@@ -196,6 +196,18 @@ def test_tuning_table_validation(L):
     assert L.gsf_tuning_reset() == 0
     assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
     assert (got.merge_sweeps, got.sweep_blocks) == (1, 512)
+
+
+def test_default_tuning_entries(L):
+    """FP32 cores of 2^26 voxels and more default to the merged sweep's
+    1-row x 16-wave block (the measured best on the 512x512x1024 cube); every
+    other entry to 1 x 8."""
+    assert L.gsf_tuning_reset() == 0
+    got = B.Tuning()
+    for cls, dt, shape in ((28, 0, 2), (26, 0, 2), (25, 0, 0), (28, 1, 0), (28, 2, 0), (10, 0, 0)):
+        assert L.gsf_tuning_get(cls, dt, ctypes.byref(got)) == 0
+        assert got.merged_shape == shape, (cls, dt)
+        assert (got.merge_sweeps, got.sweep_blocks, got.pair_spectral) == (1, 512, 1)
 
 
 def test_size_class(L):

@@ -29,7 +29,7 @@ BANKS = {
     # pass); radius 12 then has its own pass
     "cfg0": [(1.0, 1.0), (2.0, 2.0), (2.0, 4.0)],
 }
-TUNINGS = [dict(merged_shape=0), dict(merged_shape=1), dict(merged_shape=2),
+TUNINGS = [dict(merged_shape=0), dict(merged_shape=1), dict(merged_shape=2), dict(merged_shape=3),
            dict(merged_shape=0, sweep_blocks=64), dict(merged_shape=1, sweep_blocks=4096),
            dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5), dict(pair_spectral=0)]
 
