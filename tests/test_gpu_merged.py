@@ -107,3 +107,26 @@ def test_tuning_table_is_per_size_class_and_dtype():
     b = B.find(_gpu(d, torch.float16), BANKS["six"], BOX, 4.0, want_F=True)
     for j in range(6):
         assert torch.equal(a["F"][0][j], b["F"][0][j])
+
+
+# every compiled pair of spectral radii ({3,6}, {3,12}, {6,12}, {6,24},
+# {12,24}, {3,24}) as two filters of different sigma_z
+PAIR_BANKS = [[(1.0, 1.0), (1.0, 2.0)], [(1.0, 1.0), (2.0, 4.0)], [(2.0, 2.0), (2.0, 4.0)],
+              [(2.0, 2.0), (2.0, 8.0)], [(1.0, 4.0), (2.0, 8.0)], [(1.0, 8.0), (1.0, 1.0)]]
+# dims below the radii, single voxels, ragged z (element path) and z a
+# multiple of 4 (aligned path)
+ODD = [(5, 7, 9), (1, 1, 1), (3, 70, 257), (33, 17, 300), (2, 3, 64), (40, 9, 65), (70, 2, 1)]
+
+
+@pytest.mark.parametrize("shape", ODD)
+def test_paired_spectral_pass_odd_shapes(shape):
+    """One read of the cube for two spectral passes gives F bit for bit equal
+    to the single-pass path (gsf_filter3d) for every compiled radius pair."""
+    d = synth.make_noise(shape, seed=sum(shape) + 7) + 0.25
+    g = _gpu(d)
+    for bank in PAIR_BANKS:
+        out = B.find(g, bank, (4, 4, 8), 4.0, want_F=True)
+        torch.cuda.synchronize()
+        for j, f in enumerate(bank):
+            assert torch.equal(out["F"][0][j], B.filter3d(g, f)), (shape, bank, f)
+    log(f"  {shape}: six radius pairs bit-identical to single passes")
