@@ -3,8 +3,9 @@
 // The 3-D filter is the outer product gxy (x) gxy (x) gz, so Eq. 2 is applied
 // as a spectral pass followed by a fused spatial pass:
 //   k_zpass_rows<R>: T1 = gz * d along z (contiguous).  A block walks 16
-//     rows of a 1024-wide z chunk, staging each row with its +-R halo in a
-//     double-buffered LDS tile one row ahead of use (coalesced loads); every
+//     rows of a 1024-wide z chunk (256 wide for short rows), staging each
+//     row with its +-R halo in a double-buffered LDS tile one row ahead of
+//     use (coalesced loads); every
 //     lane then holds a (4 + 2R)-wide window in registers (ds_read_b128) and
 //     produces 4 consecutive outputs, so each staged value feeds up to
 //     4(2R+1) FMAs.
@@ -33,7 +34,6 @@ namespace gsf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kZOut = 4 * kThreads;   // z outputs per k_zpass_r block
 
 // Four consecutive elements (16-byte aligned for FP32, 8-byte for 16-bit).
 template <typename St>
@@ -64,8 +64,9 @@ __device__ __forceinline__ void store4(St *p, const float (&v)[4])
     }
 }
 
-// The spectral pass: a block walks kZRows consecutive rows of one 1024-wide
-// z chunk (four outputs per lane), loading each row one row ahead of its use
+// The spectral pass: a block of T threads walks kZRows consecutive rows of
+// one z chunk of 4T outputs (T = 256, or 64 for short rows; four outputs per
+// lane), loading each row one row ahead of its use
 // into a double-buffered FP32 LDS tile (one barrier per row).  When the row
 // lengths and the z halo are multiples of 4 (A), every row starts aligned
 // and a lane loads and stores its four values with single 4-element
@@ -75,28 +76,30 @@ __device__ __forceinline__ void store4(St *p, const float (&v)[4])
 // as a separate multiply would store them): the weighted numerator of Eq. 1.
 constexpr int kZRows = 16;
 
-template <int R, typename St, bool A, bool MUL = false>
-__global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ in,
+template <int R, typename St, bool A, bool MUL = false, int T = kThreads>
+__global__ __launch_bounds__(T) void k_zpass_rows(const St *__restrict__ in,
                                                          float *__restrict__ out, int64_t nrows,
                                                          int64_t nz, int64_t NZ, int64_t zoff,
                                                          Taps t, const St *__restrict__ wv = nullptr)
 {
+    static_assert(2 * R <= T, "halo lanes");
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
-    constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
+    constexpr int ZO = 4 * T;                        // z outputs per block
+    constexpr int TL = ZO + 4 * NW + 4;           // tile length, float4 multiple
     constexpr uint32_t SZ = sizeof(St);
     __shared__ float4 tile4[2][TL / 4];
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * kZRows;
     const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
-    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    const int64_t z0 = (int64_t)blockIdx.y * ZO;
     // core z of the output maps to input z + zoff in rows of NZ values
     const int64_t zm = z0 + 4 * tid;                 // this lane's four values and outputs
     const bool mine = zm < nz;                       // outputs inside the core (A)
     const bool load = zm + zoff < NZ;                // inputs inside the array (A)
-    // halo: lanes 0 .. 2R-1 fetch z0 - R + lane (left) and z0 + kZOut + lane - R (right)
-    const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
+    // halo: lanes 0 .. 2R-1 fetch z0 - R + lane (left) and z0 + ZO + lane - R (right)
+    const int64_t zh = tid < R ? z0 - R + tid : z0 + ZO + (tid - R);
     const bool halo = tid < 2 * R && zh + zoff >= 0 && zh + zoff < NZ;
-    const int th = tid < R ? tid : kZOut + tid;      // its tile index
+    const int th = tid < R ? tid : ZO + tid;      // its tile index
     // element form: byte offsets inside a row (zm + zoff >= 0; a row is
     // below 2^31 bytes)
     const uint32_t om = (uint32_t)((zm + zoff) * SZ);
@@ -175,30 +178,32 @@ __global__ __launch_bounds__(kThreads) void k_zpass_rows(const St *__restrict__ 
 // tap order as k_zpass_rows<R1>, so both outputs are bit for bit those of
 // the single passes.  Used when two filter groups of one call have
 // different sigma_z (the cube is then read once instead of twice).
-template <int R1, int R2, typename St, bool A>
-__global__ __launch_bounds__(kThreads) void k_zpass2_rows(const St *__restrict__ in,
+template <int R1, int R2, typename St, bool A, int T = kThreads>
+__global__ __launch_bounds__(T) void k_zpass2_rows(const St *__restrict__ in,
                                                           float *__restrict__ out1,
                                                           float *__restrict__ out2,
                                                           int64_t nrows, int64_t nz, int64_t NZ,
                                                           int64_t zoff, Taps t1, Taps t2)
 {
     static_assert(R1 < R2, "radii ascending");
+    static_assert(2 * R2 <= T, "halo lanes");
     constexpr int R = R2;
     constexpr int NW = (4 + 2 * R + 3) / 4;          // float4 window per lane
-    constexpr int TL = kZOut + 4 * NW + 4;           // tile length, float4 multiple
+    constexpr int ZO = 4 * T;                        // z outputs per block
+    constexpr int TL = ZO + 4 * NW + 4;           // tile length, float4 multiple
     constexpr int DR = R2 - R1;
     constexpr uint32_t SZ = sizeof(St);
     __shared__ float4 tile4[2][TL / 4];
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * kZRows;
     const int64_t r1 = r0 + kZRows < nrows ? r0 + kZRows : nrows;
-    const int64_t z0 = (int64_t)blockIdx.y * kZOut;
+    const int64_t z0 = (int64_t)blockIdx.y * ZO;
     const int64_t zm = z0 + 4 * tid;
     const bool mine = zm < nz;
     const bool load = zm + zoff < NZ;
-    const int64_t zh = tid < R ? z0 - R + tid : z0 + kZOut + (tid - R);
+    const int64_t zh = tid < R ? z0 - R + tid : z0 + ZO + (tid - R);
     const bool halo = tid < 2 * R && zh + zoff >= 0 && zh + zoff < NZ;
-    const int th = tid < R ? tid : kZOut + tid;
+    const int th = tid < R ? tid : ZO + tid;
     const uint32_t om = (uint32_t)((zm + zoff) * SZ);
     const uint32_t oh = halo ? (uint32_t)((zh + zoff) * SZ) : kOOB;
     const uint32_t os = (uint32_t)(zm * sizeof(float));
@@ -443,6 +448,18 @@ const char *kernel_name(const char *base, int r)
     return tab[base[2] == 'z' ? 0 : 1][r].c_str();
 }
 
+// Block width of a spectral pass over rows of nz outputs with halo r: 256
+// threads (1024 outputs per block) or 64 (256 outputs), whichever stages the
+// fewest values per row, ceil(nz / outputs) (outputs + 2r); ties to the wide
+// block.  A 1024-wide block over a short row leaves most lanes idle (rows of
+// 112 values, the smallest halo sub-cubes, use 11% of them).
+inline bool zpass_narrow(int64_t nz, int r)
+{
+    const int64_t wide = (nz + 4 * kThreads - 1) / (4 * kThreads) * (4 * kThreads + 2 * r);
+    const int64_t narrow = (nz + 4 * 64 - 1) / (4 * 64) * (4 * 64 + 2 * r);
+    return narrow < wide;
+}
+
 template <int R, typename St, bool MUL>
 hipError_t zpass_impl(const void *in_, void *out_, Dims d, const Halo &h, const Taps &tz,
                       hipStream_t s, const void *w_)
@@ -451,15 +468,25 @@ hipError_t zpass_impl(const void *in_, void *out_, Dims d, const Halo &h, const 
     const St *w = (const St *)w_;
     float *out = (float *)out_;
     const int64_t rows = h.NX * h.NY;
-    const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     prof::Scope scope(MUL ? "k_zpass_r_mul" : kernel_name<St>("k_zpass_r", R), s);
-    const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
-    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0)
-        hipLaunchKernelGGL((k_zpass_rows<R, St, true, MUL>), grid, dim3(kThreads), 0, s, in, out,
-                           rows, d.nz, h.NZ, (int64_t)h.hz, tz, w);
-    else
-        hipLaunchKernelGGL((k_zpass_rows<R, St, false, MUL>), grid, dim3(kThreads), 0, s, in, out,
-                           rows, d.nz, h.NZ, (int64_t)h.hz, tz, w);
+    const bool A = d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0;
+    auto go = [&](auto tc, auto ac) {
+        constexpr int T = decltype(tc)::value;
+        constexpr bool AL = decltype(ac)::value;
+        const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows),
+                        (unsigned)((d.nz + 4 * T - 1) / (4 * T)));
+        hipLaunchKernelGGL((k_zpass_rows<R, St, AL, MUL, T>), grid, dim3(T), 0, s, in, out, rows,
+                           d.nz, h.NZ, (int64_t)h.hz, tz, w);
+    };
+    using W = std::integral_constant<int, kThreads>;
+    using N = std::integral_constant<int, 64>;
+    using Y = std::true_type;
+    using F = std::false_type;
+    if (zpass_narrow(d.nz, R)) {
+        if (A) go(N{}, Y{}); else go(N{}, F{});
+    } else {
+        if (A) go(W{}, Y{}); else go(W{}, F{});
+    }
     return hipGetLastError();
 }
 
@@ -480,17 +507,27 @@ hipError_t zpass2_impl(const void *in_, void *o1, void *o2, Dims d, const Halo &
 {
     const St *in = (const St *)in_;
     const int64_t rows = h.NX * h.NY;
-    const unsigned zt = (unsigned)((d.nz + kZOut - 1) / kZOut);
     static const std::string name = "k_zpass2_r<" + std::to_string(R1) + "," +
                                     std::to_string(R2) + store_suffix<St>() + ">";
     prof::Scope scope(name.c_str(), s);
-    const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows), zt);
-    if (d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0)
-        hipLaunchKernelGGL((k_zpass2_rows<R1, R2, St, true>), grid, dim3(kThreads), 0, s, in,
+    const bool A = d.nz % 4 == 0 && h.NZ % 4 == 0 && h.hz % 4 == 0;
+    auto go = [&](auto tc, auto ac) {
+        constexpr int T = decltype(tc)::value;
+        constexpr bool AL = decltype(ac)::value;
+        const dim3 grid((unsigned)((rows + kZRows - 1) / kZRows),
+                        (unsigned)((d.nz + 4 * T - 1) / (4 * T)));
+        hipLaunchKernelGGL((k_zpass2_rows<R1, R2, St, AL, T>), grid, dim3(T), 0, s, in,
                            (float *)o1, (float *)o2, rows, d.nz, h.NZ, (int64_t)h.hz, t1, t2);
-    else
-        hipLaunchKernelGGL((k_zpass2_rows<R1, R2, St, false>), grid, dim3(kThreads), 0, s, in,
-                           (float *)o1, (float *)o2, rows, d.nz, h.NZ, (int64_t)h.hz, t1, t2);
+    };
+    using W = std::integral_constant<int, kThreads>;
+    using N = std::integral_constant<int, 64>;
+    using Y = std::true_type;
+    using F = std::false_type;
+    if (zpass_narrow(d.nz, R2)) {
+        if (A) go(N{}, Y{}); else go(N{}, F{});
+    } else {
+        if (A) go(W{}, Y{}); else go(W{}, F{});
+    }
     return hipGetLastError();
 }
 
