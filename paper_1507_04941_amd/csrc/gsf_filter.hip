@@ -154,13 +154,17 @@ __global__ __launch_bounds__(T) void k_zpass_rows(const St *__restrict__ in,
             w[4 * j + 2] = q.z;
             w[4 * j + 3] = q.w;
         }
+        // pair form (taps symmetric bit for bit): outermost pair first, the
+        // centre last, as every spectral and spatial pass here sums
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int o = 0; o <= 2 * R; ++o) {
-            const float g = t.g[o];
+        for (int d = R; d >= 1; --d) {
+            const float g = t.g[R - d];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + o], acc[k]);
+            for (int k = 0; k < 4; ++k) acc[k] = fmaf(g, w[k + R - d] + w[k + R + d], acc[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fmaf(t.g[R], w[k + R], acc[k]);
         if constexpr (A) {
             if (mine) store4(out + r * nz + zm, acc);
         } else {
@@ -252,21 +256,35 @@ __global__ __launch_bounds__(T) void k_zpass2_rows(const St *__restrict__ in,
             w[4 * j + 2] = q.z;
             w[4 * j + 3] = q.w;
         }
+        // both radii share the centre (window entry R2 + k) and the pair sums
+        // of the inner R1 distances; each pass sums in pair form (outermost
+        // pair first, centre last), as the single passes do
+        float pr[4][R1 + 1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int d = 1; d <= R1; ++d) pr[k][d] = w[k + R2 - d] + w[k + R2 + d];
         float a1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int o = 0; o <= 2 * R1; ++o) {
-            const float g = t1.g[o];
+        for (int d = R1; d >= 1; --d) {
+            const float g = t1.g[R1 - d];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a1[k] = fmaf(g, w[DR + k + o], a1[k]);
+            for (int k = 0; k < 4; ++k) a1[k] = fmaf(g, pr[k][d], a1[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a1[k] = fmaf(t1.g[R1], w[k + R2], a1[k]);
         put(out1, r, a1);
         float a2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int o = 0; o <= 2 * R2; ++o) {
-            const float g = t2.g[o];
+        for (int d = R2; d >= 1; --d) {
+            const float g = t2.g[R2 - d];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a2[k] = fmaf(g, w[k + o], a2[k]);
+            for (int k = 0; k < 4; ++k)
+                a2[k] = fmaf(g, d <= R1 ? pr[k][d <= R1 ? d : 0] : w[k + R2 - d] + w[k + R2 + d],
+                             a2[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a2[k] = fmaf(t2.g[R2], w[k + R2], a2[k]);
         put(out2, r, a2);
     }
 }
@@ -385,9 +403,15 @@ __global__ __launch_bounds__(64 * NW) void k_yx_r(const float *__restrict__ T,
             const int sx = xp & (S - 1);                     // stage of plane xp
 #pragma unroll
             for (int q = 0; q < P; ++q) {
+                // y pass in pair form: rows at equal distance from the centre
+                // row are added first (taps symmetric bit for bit), outermost
+                // pair first, the centre last
+                const int c = wave * P + q + R;
                 float t2 = 0.0f;
 #pragma unroll
-                for (int o = 0; o < L; ++o) t2 = fmaf(t.g[o], stage[sx][wave * P + q + o][lane], t2);
+                for (int d = R; d >= 1; --d)
+                    t2 = fmaf(t.g[R - d], stage[sx][c - d][lane] + stage[sx][c + d][lane], t2);
+                t2 = fmaf(t.g[R], stage[sx][c][lane], t2);
 #pragma unroll
                 for (int k = 0; k < L; ++k) {
                     const int slot = (j + R + 1 + k) % L;

@@ -45,9 +45,10 @@ namespace merged {
 // The spatial sweep of every filter of a group that shares one spectral
 // pass (equal sigma_z), from one read of T1.  Filters i = 0..NF-1 of radii
 // R0, R1, R2 (R2 = 0: two filters): the block's LDS tile holds the rows of the
-// widest one (TY + 2 RM); filter i's y pass of row q reads the rows RM - R_i
-// + q + o (o = 0..2 R_i) of the tile, in the same tap order as k_yx_r.  Each
-// filter keeps its own register ring of partial x sums.  One unrolled turn
+// widest one (TY + 2 RM); the y pass of row q (centre tile row RM + q) adds
+// the two rows at each distance d first, once for all filters, and filter i
+// sums its taps over d = R_i .. 1 and the centre in the order k_yx_r uses.
+// Each filter keeps its own register ring of partial x sums.  One unrolled turn
 // is L = 2 RM + 1 planes for all rings: the partial sum of output plane xo
 // lives in slot (xo - p_start) mod L, which a filter of radius R_i fills
 // from plane xo - R_i to xo + R_i, writes, and clears; it is next filled from
@@ -161,6 +162,19 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
                 for (int i = 0; i < LW; ++i) rq[k][i] = rq[k + 1][i];
             load_plane(xp + D + 1, rq[D - 1]);
             const int sx = xp & (S - 1);
+            // y passes in pair form: the sums of the two rows at distance d
+            // from each output row's centre are formed once and shared by
+            // every filter of the group (radius R_i uses d <= R_i), outermost
+            // pair first, the centre last, as the single-filter sweep sums
+            float pd[P][RM + 1];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int c = wave * P + q + RM;
+                pd[q][0] = stage[sx][c][lane];
+#pragma unroll
+                for (int d = 1; d <= RM; ++d)
+                    pd[q][d] = stage[sx][c - d][lane] + stage[sx][c + d][lane];
+            }
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const int R = Rs[f];
@@ -168,9 +182,8 @@ __global__ __launch_bounds__(64 * NW) void k_yxm(const float *__restrict__ T, St
                 for (int q = 0; q < P; ++q) {
                     float t2 = 0.0f;
 #pragma unroll
-                    for (int o = 0; o <= 2 * R; ++o)
-                        t2 = fmaf(t.g[f][sym(o, R)], stage[sx][wave * P + q + RM - R + o][lane],
-                                  t2);
+                    for (int d = R; d >= 1; --d) t2 = fmaf(t.g[f][R - d], pd[q][d], t2);
+                    t2 = fmaf(t.g[f][R], pd[q][0], t2);
 #pragma unroll
                     for (int k = 0; k <= 2 * R; ++k) {
                         const int slot = (j - R + k + L) % L;
