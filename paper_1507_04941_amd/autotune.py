@@ -7,10 +7,11 @@ GPU for a workload -- one cube or a batch of sub-cubes with a filter bank --
 picks the fastest per size class by coordinate descent, caches the winners in
 a JSON file and installs them into the library's table.
 
-Coordinate descent over, in order: the spatial-sweep form (merged sweeps in
-each of the compiled block shapes, or one sweep per filter), the x split of
-the sweeps (blocks a sweep aims for), and the waves per block of the yz
-window-sum kernel.  Each candidate is timed as the median of `reps` timed
+Coordinate descent over, in order: the spectral-pass schedule (two sigma_z
+groups from one read of the cube, or one pass each), the spatial-sweep form
+(merged sweeps in each of the compiled block shapes, or one sweep per
+filter), the x split of the sweeps (blocks a sweep aims for), and the waves
+per block of the yz window-sum kernel.  Each candidate is timed as the median of `reps` timed
 rounds of `steps` gsf_find calls after a warm-up; candidates that do not beat
 the incumbent by more than `min_gain` (relative) are not taken, so noise does
 not move the choice.  Results never depend on the configuration beyond
@@ -125,8 +126,10 @@ def _tune_class(plan, cls: int, dtype, steps: int, reps: int, min_gain: float, l
         return ms
 
     best_ms = measure(best)
-    for axis in ("form", "sweep_blocks", "yz_waves"):
-        if axis == "form":
+    for axis in ("spectral", "form", "sweep_blocks", "yz_waves"):
+        if axis == "spectral":
+            cands = [dict(best, pair_spectral=v) for v in (1, 0)]
+        elif axis == "form":
             cands = [dict(best, **c) for c in SWEEP_FORMS]
         elif axis == "sweep_blocks":
             cands = [dict(best, sweep_blocks=v) for v in SWEEP_BLOCKS]
