@@ -254,6 +254,10 @@ typedef struct gsf_tuning {
                               ({3,6}, {3,12}, {6,12}, {6,24}, {12,24}, {3,24})
                               get both spectral passes from one read of the cube;
                               0: one spectral pass per group */
+    int32_t x_exits;       /* 1 (default): the statistics' x walk stops its last
+                              ring turn at the first 16-step boundary past the
+                              cube (fewer wasted steps, more registers); 0: whole
+                              turns */
 } gsf_tuning;
 
 /* Size class of a cube core: floor(log2(nx*ny*nz)), 0..40; -1 if invalid. */
@@ -270,7 +274,7 @@ gsf_status gsf_tuning_set(int32_t size_class, gsf_dtype dtype, const gsf_tuning 
 gsf_status gsf_tuning_get(int32_t size_class, gsf_dtype dtype, gsf_tuning *cfg);
 
 /* Every entry back to the defaults (the values above, except merged_shape 2
- * for FP32 cores of 2^26 voxels or more). */
+ * for FP32 and 3 for 16-bit cores of 2^26 voxels or more). */
 gsf_status gsf_tuning_reset(void);
 
 /* ---- Kernel timing (measurement aid) ---- */

@@ -10,8 +10,9 @@ a JSON file and installs them into the library's table.
 Coordinate descent over, in order: the spectral-pass schedule (two sigma_z
 groups from one read of the cube, or one pass each), the spatial-sweep form
 (merged sweeps in each of the compiled block shapes, or one sweep per
-filter), the x split of the sweeps (blocks a sweep aims for), and the waves
-per block of the yz window-sum kernel.  Each candidate is timed as the median of `reps` timed
+filter), the x split of the sweeps (blocks a sweep aims for), the waves
+per block of the yz window-sum kernel, and whether the x walk exits its
+last ring turn early.  Each candidate is timed as the median of `reps` timed
 rounds of `steps` gsf_find calls after a warm-up; candidates that do not beat
 the incumbent by more than `min_gain` (relative) are not taken, so noise does
 not move the choice.  Results never depend on the configuration beyond
@@ -35,7 +36,7 @@ import torch
 from . import binding as B
 
 DEFAULT = {"merge_sweeps": 1, "merged_shape": 0, "sweep_blocks": 512, "yz_waves": 0,
-           "pair_spectral": 1}
+           "pair_spectral": 1, "x_exits": 1}
 SWEEP_FORMS = [dict(merge_sweeps=1, merged_shape=0), dict(merge_sweeps=1, merged_shape=1),
                dict(merge_sweeps=1, merged_shape=2), dict(merge_sweeps=1, merged_shape=3),
                dict(merge_sweeps=0, merged_shape=0)]
@@ -126,9 +127,11 @@ def _tune_class(plan, cls: int, dtype, steps: int, reps: int, min_gain: float, l
         return ms
 
     best_ms = measure(best)
-    for axis in ("spectral", "form", "sweep_blocks", "yz_waves"):
+    for axis in ("spectral", "form", "sweep_blocks", "yz_waves", "x_exits"):
         if axis == "spectral":
             cands = [dict(best, pair_spectral=v) for v in (1, 0)]
+        elif axis == "x_exits":
+            cands = [dict(best, x_exits=v) for v in (1, 0)]
         elif axis == "form":
             cands = [dict(best, **c) for c in SWEEP_FORMS]
         elif axis == "sweep_blocks":

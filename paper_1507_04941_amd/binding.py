@@ -46,7 +46,7 @@ class Cube(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("merge_sweeps", ctypes.c_int32), ("merged_shape", ctypes.c_int32),
                 ("sweep_blocks", ctypes.c_int32), ("yz_waves", ctypes.c_int32),
-                ("pair_spectral", ctypes.c_int32)]
+                ("pair_spectral", ctypes.c_int32), ("x_exits", ctypes.c_int32)]
 
 
 class GsfError(RuntimeError):
@@ -371,7 +371,7 @@ def tuning_set(cfg: dict, size_class: int = -1, dtype=torch.float32) -> None:
     """Install a tuning entry (keys of gsf_tuning) for a size class (-1: all)."""
     t = Tuning(int(cfg.get("merge_sweeps", 1)), int(cfg.get("merged_shape", 0)),
                int(cfg.get("sweep_blocks", 512)), int(cfg.get("yz_waves", 0)),
-               int(cfg.get("pair_spectral", 1)))
+               int(cfg.get("pair_spectral", 1)), int(cfg.get("x_exits", 1)))
     _check(lib().gsf_tuning_set(int(size_class), _DTYPES[dtype], ctypes.byref(t)))
 
 

@@ -62,12 +62,16 @@ struct Box {
 //                 one that walks the fewest columns for the cube's depth)
 //   pair_spectral 1: two spectral-pass groups with a compiled radius pair
 //                 share one read of the cube; 0: one spectral pass each
+//   x_exits       1: the x walk's last ring turn stops at the first 16-step
+//                 boundary past the end; 0: it runs whole turns
+// (the table's defaults per storage type and size class: gsf_api.cpp)
 struct Tune {
     int merge = 1;
     int merged_shape = 0;
     int sweep_blocks = 512;
     int yz_waves = 0;
     int pair_spectral = 1;
+    int x_exits = 1;
 };
 
 // The configuration of the call being enqueued on this thread: the API layer

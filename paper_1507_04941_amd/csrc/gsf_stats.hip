@@ -98,6 +98,7 @@ __device__ __forceinline__ float zwin(double u, double v, double *q, int lane, i
 // at 3 waves per SIMD.
 constexpr int kAhead = 16;    // rows the y walk loads before use
 constexpr int kAheadX = 4;    // planes the x walk loads before use
+constexpr int kXChunk = 16;   // steps between the x walk's exit tests (EXITS)
 
 // One wave per (x, 64-wide z strip); 4 independent waves per block.
 // Requires bz <= 65 so the strip plus its window spans at most 128 columns.
@@ -500,7 +501,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_span(const E *c, int p, 
 // 32-bit: every BX steps the kernel sets up descriptors over the next BX
 // planes of each stream and steps through them with scalar offsets, which
 // needs BX + 1 planes to span less than 2^31 bytes.
-template <int BX, typename St, bool STATS>
+//
+// The walk runs whole ring turns: after the last entering plane the rest of
+// the last turn reads empty ranges and emits nothing.  With EXITS the last
+// turn stops at the first 16-step boundary past the end instead (a uniform
+// exit between unrolled chunks), which saves up to 48 steps on small cubes
+// and costs registers (fewer waves per SIMD); the tuning table chooses.
+template <int BX, typename St, bool STATS, bool EXITS = false>
 __global__ __launch_bounds__(kThreads) void k_box_x_select(
     const float2 *__restrict__ G, const St *__restrict__ F,
     int64_t nx64, int64_t ny64, int64_t nz64, int by, int bz, const double *__restrict__ shift,
@@ -509,6 +516,9 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
 #pragma clang fp contract(off)
     constexpr int AX = BX < kAheadX ? BX : kAheadX;   // prefetch depth, at most the ring length
     static_assert(BX % AX == 0 && BX <= 64, "ring length");
+    constexpr int XQ = BX < kXChunk ? BX : kXChunk;   // steps per unrolled chunk
+    constexpr int NQ = BX / XQ;
+    static_assert(NQ == 1 || NQ == 2 || NQ == 4, "chunks per turn");
     const int nx = (int)nx64, ny = (int)ny64, nz = (int)nz64;
     const int y = blockIdx.y;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -573,46 +583,70 @@ __global__ __launch_bounds__(kThreads) void k_box_x_select(
         const uint32_t pbf = opaque(fplane_b);
         const __amdgpu_buffer_rsrc_t rg = plane_span(G, ga, BX, nx, plane);
         const __amdgpu_buffer_rsrc_t rfv = plane_span(F, fb, BX, nx, plane);
+        // the turn as NQ unrolled chunks of XQ steps; with EXITS the walk
+        // leaves after the chunk that passes the last entering plane (a
+        // uniform test between chunks, so every ring index stays static)
+        auto chunk = [&](auto cc) __attribute__((always_inline)) {
+            constexpr int c = decltype(cc)::value;
 #pragma clang loop unroll(full)
-        for (int j = 0; j < BX; ++j) {
-            const float g1 = pg[j % AX].x, g2 = pg[j % AX].y;
-            const raw_t<St> fraw = pfv[j % AX];
-            const int xf = fa + j;
-            pg[j % AX] = buf_ld2(rg, offg + (uint32_t)j * pbg);
-            pfv[j % AX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
-            s1 += (double)g1 - (double)r1[j];
-            s2 += (double)g2 - (double)r2[j];
-            r1[j] = g1;
-            r2[j] = g2;
-            const int x = xo + j;
-            if (x >= 0 && x < nx) {
-                // n = cx * cy * cz, cx the clipped window length along x; away
-                // from the x faces cx = BX and 1/BX is exact
-                const int cx = win_len32(x, nx, BX);
-                double icx = 1.0 / BX;
-                if (cx != BX) icx = 1.0 / (double)cx;   // IEEE division: correctly rounded
-                const double inv_n = inv_yz * icx;
-                const double m1 = s1 * inv_n;
-                double var = s2 * inv_n - m1 * m1;
-                var = var < 0.0 ? 0.0 : var;
-                const float mf = (float)(s + m1);
-                const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
-                const uint32_t so = off + (uint32_t)(x - xb) * pb;
-                if (STATS) {   // compiled out when only masks are wanted
-                    if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
-                    if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
+            for (int jj = 0; jj < XQ; ++jj) {
+                const int j = c * XQ + jj;
+                const float g1 = pg[j % AX].x, g2 = pg[j % AX].y;
+                const raw_t<St> fraw = pfv[j % AX];
+                const int xf = fa + j;
+                pg[j % AX] = buf_ld2(rg, offg + (uint32_t)j * pbg);
+                pfv[j % AX] = sbuf_ld_raw<St>(rfv, offf + (uint32_t)(xf >= 0 ? xf - fb : BX) * pbf);
+                s1 += (double)g1 - (double)r1[j];
+                s2 += (double)g2 - (double)r2[j];
+                r1[j] = g1;
+                r2[j] = g2;
+                const int x = xo + j;
+                if (x >= 0 && x < nx) {
+                    // n = cx * cy * cz, cx the clipped window length along x; away
+                    // from the x faces cx = BX and 1/BX is exact
+                    const int cx = win_len32(x, nx, BX);
+                    double icx = 1.0 / BX;
+                    if (cx != BX) icx = 1.0 / (double)cx;   // IEEE division: correctly rounded
+                    const double inv_n = inv_yz * icx;
+                    const double m1 = s1 * inv_n;
+                    double var = s2 * inv_n - m1 * m1;
+                    var = var < 0.0 ? 0.0 : var;
+                    const float mf = (float)(s + m1);
+                    const float sf = __builtin_amdgcn_sqrtf((float)var);   // std is stored in FP32
+                    const uint32_t so = off + (uint32_t)(x - xb) * pb;
+                    if (STATS) {   // compiled out when only masks are wanted
+                        if (mean) buf_st(plane_span(mean, xb, BX, nx, plane), mf, so);
+                        if (stdev) buf_st(plane_span(stdev, xb, BX, nx, plane), sf, so);
+                    }
+                    if (mask) {
+                        const float fv = from_raw<St>(fraw);
+                        const bool bit = live && (double)fv > (double)mf + k * (double)sf;
+                        const uint64_t word = __ballot(bit);
+                        if ((threadIdx.x & 63) == 0 && live)
+                            buf_st2(rmask, __uint_as_float((uint32_t)word),
+                                    __uint_as_float((uint32_t)(word >> 32)),
+                                    mword_b + (uint32_t)x * mplane_b);
+                    }
                 }
-                if (mask) {
-                    const float fv = from_raw<St>(fraw);
-                    const bool bit = live && (double)fv > (double)mf + k * (double)sf;
-                    const uint64_t word = __ballot(bit);
-                    if ((threadIdx.x & 63) == 0 && live)
-                        buf_st2(rmask, __uint_as_float((uint32_t)word),
-                                __uint_as_float((uint32_t)(word >> 32)),
-                                mword_b + (uint32_t)x * mplane_b);
-                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
+        };
+        chunk(std::integral_constant<int, 0>{});
+        if constexpr (EXITS) {
+            if (p0 + XQ >= nsteps) break;
+        }
+        if constexpr (NQ > 1) {
+            chunk(std::integral_constant<int, 1>{});
+            if constexpr (EXITS) {
+                if (p0 + 2 * XQ >= nsteps) break;
+            }
+        }
+        if constexpr (NQ > 2) {
+            chunk(std::integral_constant<int, 2>{});
+            if constexpr (EXITS) {
+                if (p0 + 3 * XQ >= nsteps) break;
+            }
+            chunk(std::integral_constant<int, 3>{});
         }
     }
 }
@@ -702,14 +736,21 @@ hipError_t box_x_select(const float *G, const void *F, Dims d, Box b,
 {
     const dim3 grid((unsigned)((d.nz + kThreads - 1) / kThreads), (unsigned)d.ny);
     prof::Scope scope(x_name<St>(BX), s);
-    if (mean || stdev)
-        hipLaunchKernelGGL((k_box_x_select<BX, St, true>), grid, dim3(kThreads), 0, s,
-                           (const float2 *)G,
-                           (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
-    else
-        hipLaunchKernelGGL((k_box_x_select<BX, St, false>), grid, dim3(kThreads), 0, s,
-                           (const float2 *)G,
-                           (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift, mean, stdev, mask, k);
+    const bool exits = active_tune().x_exits != 0;
+    auto go = [&](auto stc, auto exc) {
+        constexpr bool ST = decltype(stc)::value;
+        constexpr bool EX = decltype(exc)::value;
+        hipLaunchKernelGGL((k_box_x_select<BX, St, ST, EX>), grid, dim3(kThreads), 0, s,
+                           (const float2 *)G, (const St *)F, d.nx, d.ny, d.nz, b.by, b.bz, shift,
+                           mean, stdev, mask, k);
+    };
+    using T = std::true_type;
+    using N = std::false_type;
+    if (mean || stdev) {
+        if (exits) go(T{}, T{}); else go(T{}, N{});
+    } else {
+        if (exits) go(N{}, T{}); else go(N{}, N{});
+    }
     return hipGetLastError();
 }
 

@@ -173,25 +173,26 @@ def test_find_validation(L):
 
 
 def test_tuning_table_validation(L):
-    t = B.Tuning(1, 0, 512, 0, 1)
+    t = B.Tuning(1, 0, 512, 0, 1, 1)
     assert L.gsf_tuning_set(-1, 0, ctypes.byref(t)) == 0
-    for bad in (B.Tuning(2, 0, 512, 0, 1), B.Tuning(1, 4, 512, 0, 1), B.Tuning(1, -1, 512, 0, 1),
-                B.Tuning(1, 0, 63, 0, 1), B.Tuning(1, 0, 70000, 0, 1), B.Tuning(1, 0, 512, 4, 1),
-                B.Tuning(1, 0, 512, 0, 2)):
+    for bad in (B.Tuning(2, 0, 512, 0, 1, 0), B.Tuning(1, 4, 512, 0, 1, 0),
+                B.Tuning(1, -1, 512, 0, 1, 0), B.Tuning(1, 0, 63, 0, 1, 0),
+                B.Tuning(1, 0, 70000, 0, 1, 0), B.Tuning(1, 0, 512, 4, 1, 0),
+                B.Tuning(1, 0, 512, 0, 2, 0), B.Tuning(1, 0, 512, 0, 1, 2)):
         assert L.gsf_tuning_set(-1, 0, ctypes.byref(bad)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(41, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(-2, 0, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(3, 7, ctypes.byref(t)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_set(3, 0, None) == B.GSF_ERR_INVALID_ARG
-    t2 = B.Tuning(0, 2, 4096, 5, 0)
+    t2 = B.Tuning(0, 2, 4096, 5, 0, 1)
     assert L.gsf_tuning_set(20, 1, ctypes.byref(t2)) == 0
     got = B.Tuning()
     assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
     assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves,
-            got.pair_spectral) == (0, 2, 4096, 5, 0)
+            got.pair_spectral, got.x_exits) == (0, 2, 4096, 5, 0, 1)
     assert L.gsf_tuning_get(20, 0, ctypes.byref(got)) == 0
     assert (got.merge_sweeps, got.merged_shape, got.sweep_blocks, got.yz_waves,
-            got.pair_spectral) == (1, 0, 512, 0, 1)
+            got.pair_spectral, got.x_exits) == (1, 0, 512, 0, 1, 1)
     assert L.gsf_tuning_get(-1, 0, ctypes.byref(got)) == B.GSF_ERR_INVALID_ARG
     assert L.gsf_tuning_reset() == 0
     assert L.gsf_tuning_get(20, 1, ctypes.byref(got)) == 0
@@ -199,15 +200,17 @@ def test_tuning_table_validation(L):
 
 
 def test_default_tuning_entries(L):
-    """FP32 cores of 2^26 voxels and more default to the merged sweep's
-    1-row x 16-wave block (the measured best on the 512x512x1024 cube); every
-    other entry to 1 x 8."""
+    """Cores of 2^26 voxels and more default to the merged sweep's block
+    measured best on the 512x512x1024 cube (FP32 1 row x 16 waves, 16-bit 2
+    rows x 4 waves); every other entry to 1 x 8; the x walk's early exit is
+    on everywhere."""
     assert L.gsf_tuning_reset() == 0
     got = B.Tuning()
-    for cls, dt, shape in ((28, 0, 2), (26, 0, 2), (25, 0, 0), (28, 1, 0), (28, 2, 0), (10, 0, 0)):
+    for cls, dt, shape in ((28, 0, 2), (26, 0, 2), (25, 0, 0), (28, 1, 3), (28, 2, 3), (25, 1, 0),
+                           (10, 0, 0)):
         assert L.gsf_tuning_get(cls, dt, ctypes.byref(got)) == 0
         assert got.merged_shape == shape, (cls, dt)
-        assert (got.merge_sweeps, got.sweep_blocks, got.pair_spectral) == (1, 512, 1)
+        assert (got.merge_sweeps, got.sweep_blocks, got.pair_spectral, got.x_exits) == (1, 512, 1, 1)
 
 
 def test_size_class(L):

@@ -31,7 +31,7 @@ BANKS = {
 }
 TUNINGS = [dict(merged_shape=0), dict(merged_shape=1), dict(merged_shape=2), dict(merged_shape=3),
            dict(merged_shape=0, sweep_blocks=64), dict(merged_shape=1, sweep_blocks=4096),
-           dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5), dict(pair_spectral=0)]
+           dict(merge_sweeps=0), dict(yz_waves=3), dict(yz_waves=5), dict(pair_spectral=0), dict(x_exits=0)]
 
 
 @pytest.fixture(autouse=True)
